@@ -1,0 +1,128 @@
+"""Exact rational versions of Alg. 1 (PCG-HS) and Alg. 3-6 (s-step PCG).
+
+TEST INFRASTRUCTURE ONLY.  Pure Python with ``fractions.Fraction`` for tiny
+dense problems (n up to a few dozen): every operation is exact, so the s-step
+iterate x_i must EQUAL the standard PCG iterate x_{i*s} (both minimise the
+A-norm of the error over the same preconditioned Krylov space; Sec. II-A), and
+both reach the exact solution after n standard steps.
+
+The matrix A and the diagonal preconditioner B are given as integer/Fraction
+lists.  Index names follow the paper (1-based in comments).
+"""
+from __future__ import annotations
+
+from fractions import Fraction as Fr
+
+
+def _mv(A, x):
+    return [sum((a * b for a, b in zip(row, x)), Fr(0)) for row in A]
+
+
+def _dot(a, b):
+    return sum((p * q for p, q in zip(a, b)), Fr(0))
+
+
+def _binv(bdiag, v):
+    return [vi / di for vi, di in zip(v, bdiag)]
+
+
+def pcg(A, b, bdiag, iters):
+    """Alg. 1 for exactly ``iters`` steps (or until r = 0).  Returns [x_0, x_1, ...]."""
+    n = len(b)
+    x = [Fr(0)] * n
+    r = list(map(Fr, b))                       # r0 = b - A x0, x0 = 0
+    u = _binv(bdiag, r)                        # u0 = B^{-1} r0
+    p = list(u)                                # p0 = u0
+    xs = [list(x)]
+    ur = _dot(u, r)
+    for _ in range(iters):
+        if all(v == 0 for v in r):
+            break
+        s = _mv(A, p)                          # s_k = A p_k
+        alpha = ur / _dot(p, s)
+        x = [xi + alpha * pi for xi, pi in zip(x, p)]
+        r = [ri - alpha * si for ri, si in zip(r, s)]
+        u = _binv(bdiag, r)
+        ur_new = _dot(u, r)
+        beta = ur_new / ur
+        p = [ui + beta * pi for ui, pi in zip(u, p)]
+        ur = ur_new
+        xs.append(list(x))
+    return xs
+
+
+def _solve(M, rhs):
+    """Exact Gaussian elimination (M is SPD here, no pivoting needed)."""
+    s = len(M)
+    a = [list(row) + [rhs[i]] for i, row in enumerate(M)]
+    for c in range(s):
+        piv = a[c][c]
+        for i in range(c + 1, s):
+            f = a[i][c] / piv
+            for j in range(c, s + 1):
+                a[i][j] -= f * a[c][j]
+    y = [Fr(0)] * s
+    for i in range(s - 1, -1, -1):
+        y[i] = (a[i][s] - sum((a[i][j] * y[j] for j in range(i + 1, s)), Fr(0))) / a[i][i]
+    return y
+
+
+def sstep(A, b, bdiag, s, outer):
+    """Alg. 3 for ``outer`` outer iterations.  Returns a dict with the iterates
+    x_i and, per iteration, vm, alpha, beta and W (exact)."""
+    n = len(b)
+    x = [Fr(0)] * n
+    r = list(map(Fr, b))
+    Pold = None                                 # P1 = 0
+    xs, vms, alphas, betas, Ws = [list(x)], [], [], [], []
+    alpha_prev = W_prev = None
+    for k in range(outer):
+        # Alg. 4: P(:,1) = B^{-1} r, then alternate A and B^{-1}
+        cols = [None] * (2 * s)
+        cols[0] = _binv(bdiag, r)
+        pin, pout = 1, s + 1
+        for j in range(2, 2 * s + 1):
+            src = cols[pin - 1]
+            cols[pout - 1] = _mv(A, src) if j % 2 == 0 else _binv(bdiag, src)
+            pin, pout = pout, pin + 1
+        # Alg. 5
+        vm = [_dot(cols[c], r) for c in range(s)] + [_dot(cols[c], cols[2 * s - 1]) for c in range(s)]
+        # W(i,j) = vm(i+j)
+        H = [[vm[i + j + 1] for j in range(s)] for i in range(s)]
+        if k == 0:
+            beta = [[Fr(0)] * s for _ in range(s)]
+            W = H
+        else:
+            # Alg. 6: moment recurrence for rhs(s..2s-1), b1(i,j) = -rhs(i+j-1)
+            rhs = [Fr(0)] * (2 * s - 1)
+            for i in range(1, s + 1):
+                t = vm[i - 1]
+                for j in range(1, i):
+                    t += rhs[s - 1 + j - 1] * alpha_prev[s - i + j - 1]
+                rhs[s - 1 + i - 1] = -t / alpha_prev[s - 1]
+            b1 = [[-rhs[i + j] for j in range(s)] for i in range(s)]
+            bcols = [_solve(W_prev, [b1[i][j] for i in range(s)]) for j in range(s)]
+            beta = [[bcols[j][i] for j in range(s)] for i in range(s)]
+            W = [[H[i][j] - sum((b1[i][q] * beta[q][j] for q in range(s)), Fr(0))
+                  for j in range(s)] for i in range(s)]
+        alpha = _solve(W, vm[:s])
+        if Pold is not None:
+            for j in range(s):
+                for l in range(s):
+                    if beta[l][j] != 0:
+                        cols[j] = [c + po * beta[l][j] for c, po in zip(cols[j], Pold[l])]
+                        cols[s + j] = [c + po * beta[l][j]
+                                       for c, po in zip(cols[s + j], Pold[s + l])]
+        for j in range(s):
+            x = [xi + cj * alpha[j] for xi, cj in zip(x, cols[j])]
+            r = [ri - cj * alpha[j] for ri, cj in zip(r, cols[s + j])]
+        Pold = cols
+        alpha_prev, W_prev = alpha, W
+        xs.append(list(x))
+        vms.append(vm)
+        alphas.append(alpha)
+        betas.append(beta)
+        Ws.append(W)
+        if all(v == 0 for v in r):
+            break
+    return dict(x=xs, vm=vms, alpha=alphas, beta=betas, W=Ws)

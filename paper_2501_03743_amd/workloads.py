@@ -1,0 +1,149 @@
+"""Seeded synthetic inputs for the s-step CG solver (host side, numpy).
+
+This module only generates problems: grid operators in CSR form, right-hand
+sides, manufactured solutions and random coefficient fields.  It holds none
+of the solver's arithmetic, and both the HIP path and the CPU oracle take
+their inputs from it.
+
+The paper's own workload is the Poisson equation on a cube with Dirichlet
+boundary conditions and right-hand side 1 (Sec. V); the other inputs here are
+seeded synthetic stand-ins of the same kind.
+
+Operators (unscaled, lexicographic index x + nx*(y + ny*z), Dirichlet zero
+outside the grid, column indices ascending within a row):
+  2d5       diagonal 4, neighbours -1 (2D)
+  3d7       diagonal 6, neighbours -1
+  3d27      diagonal 26, the 26 neighbours -1
+  3d7_vark  -div(k grad u): face weight 2 k_p k_q / (k_p + k_q), weight k_p on
+            faces to the boundary, diagonal = sum of the six face weights
+"""
+from __future__ import annotations
+
+import numpy as np
+
+DEFAULT_COEF = {"2d5": (4.0, -1.0), "3d7": (6.0, -1.0), "3d27": (26.0, -1.0)}
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.default_rng(seed)
+
+
+def normal_rhs(n: int, seed: int) -> np.ndarray:
+    """b ~ N(0, 1), FP64."""
+    return rng(seed).standard_normal(n)
+
+
+def uniform_solution(n: int, seed: int) -> np.ndarray:
+    """x* ~ U(-1, 1), FP64."""
+    return rng(seed).uniform(-1.0, 1.0, n)
+
+
+def _grid(shape):
+    if len(shape) == 2:
+        return int(shape[0]), int(shape[1]), 1
+    return int(shape[0]), int(shape[1]), int(shape[2])
+
+
+def stencil_csr(kind: str, shape, k=None, coef=None):
+    """(rowptr int32[n+1], colind int32[nnz], val float64[nnz]) of a grid operator."""
+    nx, ny, nz = _grid(shape)
+    n = nx * ny * nz
+    idx = np.arange(n, dtype=np.int64)
+    X = idx % nx
+    Y = (idx // nx) % ny
+    Z = idx // (nx * ny)
+    if kind == "3d27":
+        offs = [(dx, dy, dz) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+    elif kind == "2d5":
+        offs = [(0, -1, 0), (-1, 0, 0), (0, 0, 0), (1, 0, 0), (0, 1, 0)]
+    elif kind in ("3d7", "3d7_vark"):
+        offs = [(0, 0, -1), (0, -1, 0), (-1, 0, 0), (0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1)]
+    else:
+        raise ValueError(kind)
+    # offsets are listed in ascending index order, so per-row columns ascend
+    cols, vals, masks = [], [], []
+    d, o = coef if coef is not None else DEFAULT_COEF.get(kind, (0.0, 0.0))
+    if kind == "3d7_vark":
+        kk = np.asarray(k, dtype=np.float64).reshape(-1)
+        diag = np.zeros(n)
+    for (dx, dy, dz) in offs:
+        qx, qy, qz = X + dx, Y + dy, Z + dz
+        m = (qx >= 0) & (qx < nx) & (qy >= 0) & (qy < ny) & (qz >= 0) & (qz < nz)
+        q = np.where(m, qx + nx * (qy + ny * qz), 0)
+        if kind == "3d7_vark":
+            if (dx, dy, dz) == (0, 0, 0):
+                v = None
+            else:
+                w = np.where(m, 2.0 * kk * kk[q] / (kk + kk[q]), kk)
+                diag += w
+                v = -w
+        else:
+            v = np.full(n, d if (dx, dy, dz) == (0, 0, 0) else o)
+        cols.append(q)
+        vals.append(v)
+        masks.append(m)
+    if kind == "3d7_vark":
+        vals[3] = diag
+    M = np.stack(masks, axis=1)
+    Cc = np.stack(cols, axis=1)[M]
+    V = np.stack(vals, axis=1)[M]
+    cnt = M.sum(axis=1)
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(cnt, out=rowptr[1:])
+    if rowptr[-1] >= 2 ** 31:
+        raise ValueError("nnz exceeds int32 indexing")
+    return rowptr.astype(np.int32), Cc.astype(np.int32), V.astype(np.float64)
+
+
+def csr_matvec(csr, x):
+    """y = A x for a CSR triple (scipy), used to manufacture b = A x*."""
+    import scipy.sparse as sp
+    rowptr, colind, val = csr
+    n = len(rowptr) - 1
+    A = sp.csr_matrix((val, colind, rowptr), shape=(n, n))
+    return A @ np.asarray(x, dtype=np.float64)
+
+
+def gaussian_random_field(shape, sigma: float, ell: float, seed: int) -> np.ndarray:
+    """Stationary Gaussian field on the unit cube with squared-exponential
+    covariance sigma^2 exp(-r^2 / (2 ell^2)), by FFT spectral synthesis on a
+    periodic grid twice the size (cropped), normalised to sample std sigma."""
+    nx, ny, nz = _grid(shape)
+    g = rng(seed)
+    ext = [2 * nx, 2 * ny, 2 * nz] if nz > 1 else [2 * nx, 2 * ny]
+    h = 1.0 / (max(nx, ny, nz) + 1)
+    freqs = np.meshgrid(*[np.fft.fftfreq(m, d=h) for m in ext], indexing="ij")
+    k2 = sum(f * f for f in freqs) * (2.0 * np.pi) ** 2
+    spec = np.exp(-0.25 * k2 * ell * ell)       # sqrt of the SE spectral density (unnormalised)
+    noise = g.standard_normal(ext)
+    field = np.real(np.fft.ifftn(np.fft.fftn(noise) * spec))
+    if nz > 1:
+        field = field[:nx, :ny, :nz]
+    else:
+        field = field[:nx, :ny]
+    field = field - field.mean()
+    field *= sigma / max(field.std(), 1e-300)
+    # return in lexicographic (x fastest) order
+    return np.ascontiguousarray(field.transpose()).reshape(-1)
+
+
+def fourier_source(shape, seed: int, modes: int = 16) -> np.ndarray:
+    """f(x) = sum_m a_m prod_d sin(pi kappa_{m,d} x_d), a_m ~ N(0,1),
+    kappa ~ U{1..4}, sampled at the interior nodes x_d = (i+1) h."""
+    nx, ny, nz = _grid(shape)
+    g = rng(seed)
+    a = g.standard_normal(modes)
+    kap = g.integers(1, 5, size=(modes, 3))
+    xs = [(np.arange(m) + 1.0) / (m + 1.0) for m in (nx, ny, nz)]
+    f = np.zeros((nz, ny, nx))
+    for m in range(modes):
+        sx = np.sin(np.pi * kap[m, 0] * xs[0])
+        sy = np.sin(np.pi * kap[m, 1] * xs[1])
+        sz = np.sin(np.pi * kap[m, 2] * xs[2])
+        f += a[m] * sz[:, None, None] * sy[None, :, None] * sx[None, None, :]
+    return f.reshape(-1)
+
+
+def batch_sides(seed: int, count: int = 32, lo: int = 32, hi: int = 160) -> np.ndarray:
+    """Side lengths L_i ~ U{lo..hi} for a batch of cubic grids."""
+    return rng(seed).integers(lo, hi + 1, size=count)
