@@ -1,0 +1,263 @@
+#!/usr/bin/env python3
+"""Time-to-solution of preconditioned s-step CG on one MI355X.
+
+Workload (one "step" = one full solve): 3D 7-point constant-coefficient
+Poisson on a 128^3 grid (n = 2,097,152, Dirichlet), FP64 CSR, Jacobi
+preconditioner, s = 4, b ~ N(0, 1) from seed 0, x0 = 0, rtol 1e-8.  Inputs
+are resident in HBM before the timed region.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+The line carries the solve time, the matrix-powers kernel's achieved HBM
+bandwidth against the 8 TB/s peak (algorithmic bytes per launch over the mean
+launch time from HIP events on the library's stream), the standard-CG and
+stencil-form times for comparison, and the CPU oracle timed on a bounded
+sample of the same solve.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+N = 128
+S = 4
+RTOL = 1e-8
+SEED = 0
+MAXIT = 20000
+
+
+def algorithmic_bytes(n, nnz):
+    """Bytes one launch of each kernel class must move (FP64 values and
+    vectors, int32 indices), per the byte model of the design notes.
+      matrix power j < s: val + colind (12 nnz) + rowptr (4n) + x, AZ_j, Z_{j+1},
+                          dinv (32 n)
+      last power + moments: 12 nnz + 4 n + x, AZ_s, r (24 n) + Z(:,1..s-1) (8(s-1) n)
+      block update: Z, AZ, P_old, AP_old (32 s n) + x, r read and written (32 n)
+                    + z1 and dinv (16 n)
+    """
+    return {
+        "mpk": 12 * nnz + 4 * n + 32 * n,
+        "mpk_last": 12 * nnz + 4 * n + 24 * n + 8 * (S - 1) * n,
+        "update": 32 * S * n + 32 * n + 16 * n,
+    }
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for f in ("common.hpp", "kernels.hpp", "small_solve.hpp", "capi.hip"):
+        with open(os.path.join(ROOT, "paper_2501_03743_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(sha):
+    """HBM traffic of the matrix-powers kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_csr_mpk_3d7_128.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.strip().split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha") != sha:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(gpu_outer, budget_s=20.0):
+    """The oracle (plain C, FP64, OpenMP) on the same 128^3 CSR problem:
+    a bounded number of outer iterations, scaled to the outer-iteration count
+    of the full solve."""
+    import oracle
+    from paper_2501_03743_amd import workloads as wl
+    csr = wl.stencil_csr("3d7", (N, N, N))
+    op = oracle.Operator("csr", csr=csr)
+    b = wl.normal_rhs(N ** 3, SEED)
+    k = 2
+    t0 = time.perf_counter()
+    oracle.sstep(op, b, S, fixed_outer=k)
+    per = (time.perf_counter() - t0) / k
+    k2 = int(max(2, min(30, budget_s / max(per, 1e-6) - k)))
+    t0 = time.perf_counter()
+    oracle.sstep(op, b, S, fixed_outer=k2)
+    per = (time.perf_counter() - t0) / k2
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": per * gpu_outer, "unit": "s", "cores": cores, "kind": "oracle",
+            "sample": "%d outer iterations (s=%d) of the same 128^3 CSR solve, %.3f s each, "
+                      "scaled to the %d outer iterations of the full solve" % (k2, S, per, gpu_outer)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only-timed", action="store_true",
+                    help="only the timed solves (for profiler runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (no sharding or collectives); "
+              "use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2501_03743_amd import sstep
+    from paper_2501_03743_amd import workloads as wl
+
+    torch.cuda.set_device(0)
+    H = sstep.Handle(0)
+    n = N ** 3
+    A = H.matrix_csr_from_stencil("3d7", (N, N, N))
+    b = torch.from_numpy(wl.normal_rhs(n, SEED)).cuda()
+    x = torch.zeros_like(b)
+    torch.cuda.synchronize()
+
+    def solve(profile=False, **kw):
+        x.zero_()
+        return H.solve(A, b, x, s=kw.pop("s", S), rtol=RTOL, maxit=MAXIT, profile=profile, **kw)
+
+    for _ in range(args.warmup):
+        res = solve()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = solve()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    tts = elapsed / args.steps
+    if res.status != 0:
+        print("bench.py: solve did not converge (status %d)" % res.status, file=sys.stderr)
+        sys.exit(1)
+    if args.only_timed:
+        print(json.dumps({"tts_s": tts, "outer": res.outer}))
+        return
+
+    # kernel durations from HIP events on the library's stream (same solves, profiled)
+    prof_ms = np.zeros(4)
+    prof_n = np.zeros(4)
+    for _ in range(args.steps):
+        r = solve(profile=True)
+        prof_ms += np.array(r.profile["ms"])
+        prof_n += np.array(r.profile["launches"])
+    nnz = A.nnz
+    ab = algorithmic_bytes(n, nnz)
+    mpk_ms = prof_ms[0] / max(prof_n[0], 1)
+    last_ms = prof_ms[1] / max(prof_n[1], 1)
+    upd_ms = prof_ms[2] / max(prof_n[2], 1)
+    achieved = ab["mpk"] / (mpk_ms * 1e-3) / 1e9
+    sha = kernel_source_sha()
+    traffic = read_traffic(sha)
+
+    # comparisons (outside the timed region): standard CG, the stencil form, other s
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            rr = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps, rr
+
+    cg_t, cg_r = timed(lambda: solve(method="pcg"))
+    As = H.matrix_stencil("3d7", (N, N, N))
+    def solve_st(**kw):
+        x.zero_()
+        return H.solve(As, b, x, rtol=RTOL, maxit=MAXIT, **kw)
+    st_t, st_r = timed(lambda: solve_st(s=S))
+    stcg_t, stcg_r = timed(lambda: solve_st(method="pcg"))
+    # plain SpMV per operator form / CSR kernel variant (HIP events on the same stream)
+    def spmv_ms(M, reps=20):
+        y = torch.empty_like(b)
+        H.spmv(M, b, y)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            H.spmv(M, b, y)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+    spmv = {"csr_autotuned_ms": spmv_ms(A), "stencil_ms": spmv_ms(As)}
+    saved = os.environ.get("SSP_CSR_VARIANT")
+    for v, name in ((0, "csr_staged_ms"), (1, "csr_row_ms")):
+        os.environ["SSP_CSR_VARIANT"] = str(v)
+        Mv = H.matrix_csr_from_stencil("3d7", (N, N, N))
+        spmv[name] = spmv_ms(Mv)
+        Mv.close()
+    if saved is None:
+        del os.environ["SSP_CSR_VARIANT"]
+    else:
+        os.environ["SSP_CSR_VARIANT"] = saved
+    plain_bytes = 12 * nnz + 4 * n + 16 * n
+    spmv["csr_plain_bytes"] = plain_bytes
+    spmv["csr_best_gbs"] = plain_bytes / (min(spmv["csr_staged_ms"], spmv["csr_row_ms"]) * 1e-3) / 1e9
+    spmv["stencil_gbs"] = 16 * n / (spmv["stencil_ms"] * 1e-3) / 1e9
+
+    per_s = {}
+    for s in (1, 2, 8):
+        t, r = timed(lambda: solve(s=s), reps=2)
+        per_s[str(s)] = {"tts_s": t, "outer": r.outer, "status": r.status,
+                         "true_rel": r.true_rel}
+
+    out = {
+        "metric": "time-to-solution @rtol 1e-8 (s) + SpMV/matrix-powers HBM GB/s, s-step vs CG",
+        "value": tts,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": tts * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "3D 7-point Poisson 128^3 (n=2097152, nnz=%d), FP64 CSR, Jacobi, "
+                               "s=4, b~N(0,1) seed 0, x0=0, rtol 1e-8" % nnz,
+                   "global_batch": 1, "seq_len": None, "parallelism": "none (1 GPU)"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "matrix-powers CSR SpMV + Jacobi (power j < s)",
+                     "bytes_per_launch": ab["mpk"], "mean_launch_ms": mpk_ms},
+        "iterations": {"outer": res.outer, "cg_equiv": res.cg_equiv, "true_rel": res.true_rel},
+        "kernels": {
+            "mpk_gbs": achieved,
+            "mpk_last_gram_solve_ms": last_ms,
+            "mpk_last_gbs": ab["mpk_last"] / (last_ms * 1e-3) / 1e9,
+            "update_ms": upd_ms,
+            "update_gbs": ab["update"] / (upd_ms * 1e-3) / 1e9,
+            "kernel_ms_per_solve": (prof_ms / args.steps).tolist(),
+            "launches_per_solve": (prof_n / args.steps).tolist(),
+            "kernel_source_sha": sha,
+        },
+        "compare": {
+            "pcg_csr_tts_s": cg_t, "pcg_csr_iterations": cg_r.outer,
+            "sstep_stencil_tts_s": st_t, "sstep_stencil_outer": st_r.outer,
+            "pcg_stencil_tts_s": stcg_t, "pcg_stencil_iterations": stcg_r.outer,
+            "sstep_csr_by_s": per_s,
+            "spmv": spmv,
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(res.outer)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

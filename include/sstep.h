@@ -1,0 +1,211 @@
+/*
+ * sstep.h -- C ABI of libsstep.so: preconditioned s-step conjugate gradient
+ * (Chronopoulos-Gear) on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Bernaschi, Carrozzo, Celestini, Piperno, D'Ambra, "Communication-
+ * reduced Conjugate Gradient Variants for GPU-accelerated Clusters",
+ * Euromicro PDP 2025 (arXiv 2501.03743):
+ *   Alg. 3 (PCGs), Alg. 4 (pMPK), Alg. 5 (cvm), Alg. 6 (SW), Sec. II-A;
+ *   Alg. 1 (PCG-HS) as the standard-CG comparator.
+ *
+ * Conventions for every entry point:
+ *   - Return value: SSP_OK (0), a positive solver outcome (SSP_NOT_CONVERGED,
+ *     SSP_BREAKDOWN) or a negative error code.  No C++ exception crosses the
+ *     ABI.  After a negative return, ssp_last_error() describes the problem.
+ *   - "device" pointers are HIP device allocations on the handle's device;
+ *     "host" pointers are ordinary host memory.  The library never frees
+ *     caller memory.
+ *   - All device work is ordered on the handle's stream.  Calls that return
+ *     results to the host (ssp_solve, the query functions) synchronise that
+ *     stream; the others only enqueue work.
+ *   - A handle is not thread-safe: use one handle per host thread.
+ *   - Vectors are dense FP64 arrays of n entries; unknowns of grid operators
+ *     are numbered lexicographically, index = x + nx*(y + ny*z).
+ */
+#ifndef SSTEP_H
+#define SSTEP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ssp_handle ssp_handle;
+typedef struct ssp_matrix ssp_matrix;
+
+/* ---- status codes -------------------------------------------------------- */
+#define SSP_OK 0              /* converged: ||r||_2 <= rtol ||b||_2            */
+#define SSP_NOT_CONVERGED 1   /* iteration limit reached; x = last iterate
+                                 (Alg. 1 and Alg. 3 "did not converge")         */
+#define SSP_BREAKDOWN 2       /* non-SPD s x s Gram matrix, alpha_{i-1}(s) ~ 0 or
+                                 a non-finite value; x = last good iterate      */
+#define SSP_EINVAL (-1)       /* invalid argument                               */
+#define SSP_ENOMEM (-2)       /* device allocation failed                       */
+#define SSP_EHIP (-3)         /* HIP runtime error                              */
+#define SSP_EUNSUPPORTED (-4) /* valid but not implemented combination          */
+
+/* Largest block size s (the moment matrices are s x s). */
+#define SSP_SMAX 16
+
+/* ---- operator kinds (ssp_matrix_stencil) --------------------------------- */
+#define SSP_STENCIL_2D5 1     /* 2D 5-point; default coef {4, -1}; nz must be 1 */
+#define SSP_STENCIL_3D7 2     /* 3D 7-point; default coef {6, -1}               */
+#define SSP_STENCIL_3D27 3    /* 3D 27-point; default coef {26, -1}             */
+#define SSP_STENCIL_3D7_VARK 4/* -div(k grad u), 7-point: face weight
+                                 2 k_p k_q / (k_p + k_q), weight k_p on faces to
+                                 the boundary, diagonal = sum of the 6 weights   */
+
+/* ---- flags of ssp_matrix_csr ---------------------------------------------- */
+#define SSP_BORROW 0u         /* library keeps the caller's device arrays; they
+                                 must outlive the matrix (default)              */
+#define SSP_COPY 1u           /* library copies the arrays into its own memory  */
+#define SSP_VALIDATE 2u       /* O(nnz) check: rowptr monotone from 0, column
+                                 indices in range and ascending in each row, a
+                                 positive diagonal entry in each row            */
+
+/* ---- preconditioners ----------------------------------------------------- */
+#define SSP_PREC_NONE 0       /* B = I (Sec. V-A "no preconditioning")          */
+#define SSP_PREC_JACOBI 1     /* B = diag(A) (the weighted-Jacobi building block
+                                 of the paper's AMG smoother, Sec. III-A)       */
+
+/* ---- solver options ------------------------------------------------------ */
+#define SSP_METHOD_SSTEP 0    /* Alg. 3 with Alg. 4-6                           */
+#define SSP_METHOD_PCG 1      /* Alg. 1                                         */
+
+#define SSP_PRECISION_FP64 0
+#define SSP_PRECISION_MIXED_IR 1  /* FP32 inner s-step (matrix powers and block
+                                     updates in FP32, moments and s x s solves
+                                     in FP64) inside FP64 iterative refinement */
+
+typedef struct ssp_opts {
+  int method;          /* SSP_METHOD_*                                          */
+  int precision;       /* SSP_PRECISION_*                                       */
+  double inner_rtol;   /* MIXED_IR: relative tolerance of each inner solve      */
+  int max_refine;      /* MIXED_IR: limit on refinement steps                   */
+  int check_every;     /* outer iterations enqueued between host polls of the
+                          device status word; 0 = library default               */
+  int fixed_outer;     /* > 0: run exactly this many outer iterations with no
+                          stopping test (stops early only on breakdown); the
+                          result is SSP_OK if the residual test holds at the end */
+  int profile;         /* 1: time every kernel class with HIP events on the
+                          handle's stream (see ssp_get_profile)                 */
+  int trace_cap;       /* > 0 with the trace_* host buffers: record per outer
+                          iteration the moments vm(1..2s), alpha (s), beta (s*s,
+                          beta(l,j) at [l*s+j]) and W (s*s, row-major), for up
+                          to trace_cap iterations (synchronises every iteration;
+                          for testing)                                          */
+  double *trace_vm;    /* host, trace_cap * 2s                                  */
+  double *trace_alpha; /* host, trace_cap * s                                   */
+  double *trace_beta;  /* host, trace_cap * s * s                               */
+  double *trace_W;     /* host, trace_cap * s * s                               */
+} ssp_opts;
+
+/* ---- handle ---------------------------------------------------------------- */
+
+/* Creates a handle bound to HIP device `device` and to the caller's stream
+ * `hip_stream` (a hipStream_t; NULL = the legacy default stream).  Allocates
+ * only small control blocks; solve workspaces are allocated on first use and
+ * cached.  *h is set to NULL on failure. */
+int ssp_create(ssp_handle **h, int device, void *hip_stream);
+
+/* Frees every library-owned allocation of the handle.  Matrices created with
+ * it must be destroyed first.  NULL is accepted. */
+int ssp_destroy(ssp_handle *h);
+
+/* ---- matrices -------------------------------------------------------------- */
+
+/* Sparse SPD matrix in CSR form (Sec. III: local CSR storage).  rowptr
+ * (n+1 int32), colind (nnz int32, ascending in each row) and val (nnz FP64)
+ * are DEVICE pointers.  flags: SSP_BORROW or SSP_COPY, optionally or-ed with
+ * SSP_VALIDATE.  Builds D^-1 = 1/diag(A) for the Jacobi preconditioner.
+ * The default preconditioner is SSP_PREC_JACOBI.  Errors: SSP_EINVAL for
+ * n < 1, nnz < n, nnz >= 2^31, NULL pointers or a failed validation. */
+int ssp_matrix_csr(ssp_handle *h, int64_t n, int64_t nnz, const int32_t *rowptr,
+                   const int32_t *colind, const double *val, unsigned flags,
+                   ssp_matrix **A);
+
+/* Matrix-free grid operator (Dirichlet zero outside the grid, unscaled).
+ * For the constant-coefficient kinds `coef` is a HOST pointer to {diag, off}
+ * or NULL for the defaults above.  For SSP_STENCIL_3D7_VARK `coef` is a DEVICE
+ * pointer to the n cell coefficients k (borrowed: it must outlive the matrix).
+ * Default preconditioner SSP_PREC_JACOBI. */
+int ssp_matrix_stencil(ssp_handle *h, int kind, int nx, int ny, int nz,
+                       const double *coef, ssp_matrix **A);
+
+/* The same grid operator materialised on the device in CSR form (library-
+ * owned arrays, ascending columns), so that the CSR kernels can run on it
+ * without a host build or upload.  Arguments as for ssp_matrix_stencil. */
+int ssp_matrix_csr_from_stencil(ssp_handle *h, int kind, int nx, int ny, int nz,
+                                const double *coef, ssp_matrix **A);
+
+/* Size of a matrix (nnz = stored entries of its CSR form). */
+int ssp_matrix_info(const ssp_matrix *A, int64_t *n, int64_t *nnz);
+
+/* Device pointers of a CSR matrix (borrowed, copied or library-built);
+ * SSP_EINVAL for a matrix-free operator. */
+int ssp_matrix_csr_arrays(const ssp_matrix *A, const int32_t **rowptr,
+                          const int32_t **colind, const double **val);
+
+int ssp_matrix_destroy(ssp_matrix *A);
+
+/* SSP_PREC_NONE or SSP_PREC_JACOBI. */
+int ssp_set_preconditioner(ssp_matrix *A, int kind);
+
+/* ---- building blocks ------------------------------------------------------- */
+
+/* y = A x (DEVICE vectors of n entries).  Enqueues only. */
+int ssp_spmv(ssp_handle *h, const ssp_matrix *A, const double *x, double *y);
+
+/* Alg. 4 and Alg. 5 on their own: fills the DEVICE block P (column-major,
+ * leading dimension ld >= n, 2s columns) with P(:,1:s) = [z, Kz, ..., K^{s-1}z],
+ * z = B^-1 r, K = B^-1 A, and P(:,s+1:2s) = A P(:,1:s); and, if vm is a
+ * non-NULL HOST pointer, returns vm(1:s) = P(:,1:s)^T r and
+ * vm(s+1:2s) = P(:,1:s)^T P(:,2s) (synchronises). */
+int ssp_mpk(ssp_handle *h, const ssp_matrix *A, const double *r, int s, double *P,
+            int64_t ld, double *vm);
+
+/* ---- solve ------------------------------------------------------------------ */
+
+/* Solves A x = b.  b (n) and x (n, in: x0, out: solution) are DEVICE pointers
+ * owned by the caller.  s in 1..SSP_SMAX (and s <= n) is the block size of
+ * the s-step method (ignored by SSP_METHOD_PCG).  Stops when the recursive
+ * residual satisfies ||r||_2 <= rtol ||b||_2, tested once per outer
+ * iteration; maxit counts CG-equivalent steps (outer limit ceil(maxit/s)).
+ * opts may be NULL (defaults: s-step, FP64).  b = 0 gives x = 0 and SSP_OK.
+ * Returns SSP_OK, SSP_NOT_CONVERGED, SSP_BREAKDOWN or an error.  Blocks until
+ * the result is in x. */
+int ssp_solve(ssp_handle *h, const ssp_matrix *A, const double *b, double *x, int s,
+              double rtol, int maxit, const ssp_opts *opts);
+
+/* Outer iterations and CG-equivalent steps (s * outer) of the last solve. */
+int ssp_get_iterations(const ssp_handle *h, int *outer, int *cg_equiv);
+
+/* ||r_i||_2/||b||_2 of the last solve, i = 0 (initial) .. outer; copies at most
+ * cap entries into the HOST buffer and sets *len to the full length. */
+int ssp_get_residual_history(const ssp_handle *h, double *buf, int cap, int *len);
+
+/* ||b - A x||_2/||b||_2 computed from the returned x at the end of the last
+ * solve (for MIXED_IR: of the final FP64 iterate). */
+int ssp_get_true_residual(const ssp_handle *h, double *rel);
+
+/* Kernel-class timings of the last solve run with opts.profile = 1, measured
+ * with HIP events on the handle's stream: for each class the number of
+ * launches and the summed duration in milliseconds (HOST arrays of 4).
+ * Classes: 0 = matrix powers j < s (Alg. 4; SpMV of standard CG),
+ * 1 = last power fused with the moments (Alg. 5) and the s x s solve
+ * (Alg. 6), 2 = block update (Alg. 3; vector updates of standard CG),
+ * 3 = other (initial and true residual). */
+int ssp_get_profile(const ssp_handle *h, int *launches, double *ms);
+
+/* Text for a status code (static storage). */
+const char *ssp_status_string(int status);
+
+/* Last error message of the handle (static per handle, never NULL). */
+const char *ssp_last_error(const ssp_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SSTEP_H */

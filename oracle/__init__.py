@@ -86,6 +86,9 @@ def lib():
             _lib.orc_spd_solve.argtypes = [C.c_int, C.c_void_p, C.c_void_p]
             _lib.orc_smax.restype = C.c_int
             _lib.orc_sw.restype = C.c_int
+            _lib.orc_mpk_cvm.restype = C.c_int
+            _lib.orc_mpk_cvm.argtypes = [C.POINTER(_Op), C.c_int, C.c_void_p, C.c_int, C.c_void_p,
+                                         C.c_void_p]
             _lib.orc_sw.argtypes = [C.c_int] + [C.c_void_p] * 6
         return _lib
 
@@ -185,6 +188,16 @@ def spd_solve(W, c):
     y = np.array(c, dtype=np.float64, copy=True)
     st = lib().orc_spd_solve(W.shape[0], _ptr(W), _ptr(y))
     return st, y
+
+
+def mpk_cvm(op: "Operator", r, s, prec=PREC_JACOBI):
+    """Alg. 4 then Alg. 5: returns (P as (2s, n), vm (2s,))."""
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    P = np.zeros((2 * s, op.n))
+    vm = np.zeros(2 * s)
+    st = lib().orc_mpk_cvm(C.byref(op._op), prec, _ptr(r), s, _ptr(P), _ptr(vm))
+    assert st == OK, st
+    return P, vm
 
 
 def sw(vm, alpha_prev, W_prev):

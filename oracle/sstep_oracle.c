@@ -668,6 +668,20 @@ int orc_spd_solve(int s, const double *W, double *c) {
   return 0;
 }
 
+/* Alg. 4 followed by Alg. 5 on their own, for tests: P is n x 2s
+ * column-major, vm has 2s entries. */
+int orc_mpk_cvm(const orc_op *A, int prec, const double *r, int s, double *P, double *vm) {
+  if (!op_check(A) || s < 1 || s > ORC_SMAX) return ORC_EINVAL;
+  double *dinv = malloc((size_t)A->n * sizeof(double));
+  if (!dinv) return ORC_ENOMEM;
+  op_diag(A, dinv);
+  for (int64_t i = 0; i < A->n; ++i) dinv[i] = 1.0 / dinv[i];
+  mpk(A, prec, dinv, r, s, P);
+  cvm(A->n, s, P, r, vm);
+  free(dinv);
+  return ORC_OK;
+}
+
 /* Alg. 6 on its own, for tests: factors W_{i-1} and runs sw().  Returns 0
  * or 1 on breakdown. */
 int orc_sw(int s, const double *vm, const double *alpha_prev, const double *Wprev,

@@ -1,0 +1,888 @@
+// libsstep: the C ABI declared in include/sstep.h, on top of the gfx950
+// kernels of kernels.hpp.  Host code only orders launches on the handle's
+// stream, polls the device status word every few outer iterations and copies
+// results back; every arithmetic step of a solve runs in the kernels.
+#include "sstep.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+
+using namespace ssp;
+
+namespace {
+
+struct Workspace {
+  int64_t n = 0, ld = 0;
+  int s = 0;
+  double *P1 = nullptr, *P2 = nullptr;   // n x 2s blocks, column-major, leading dim ld
+  double *r = nullptr;
+  double *pcg_p = nullptr, *pcg_s = nullptr;
+  double *partials = nullptr;            // kGridMax x 2*kSMax
+  double *hist = nullptr;
+  int hist_cap = 0;
+};
+
+}  // namespace
+
+struct ssp_handle {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  Workspace ws;
+  DevState *st = nullptr;          // device control block
+  DevState *h_init = nullptr;      // pinned staging for the control block
+  DevState *h_read = nullptr;      // pinned readback
+  // results of the last solve
+  int last_outer = 0, last_s = 1;
+  double last_true_rel = NAN;
+  std::vector<double> last_hist;
+  // profiling
+  bool prof_on = false;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> ev_cls;
+  size_t ev_used = 0;
+  int prof_launch[4] = {0, 0, 0, 0};
+  double prof_ms[4] = {0, 0, 0, 0};
+};
+
+struct ssp_matrix {
+  ssp_handle *h = nullptr;
+  int kind = 0;                  // 0 = CSR, else SSP_STENCIL_*
+  int64_t n = 0, nnz = 0;
+  CsrArgs csr{};
+  int32_t *own_rowptr = nullptr, *own_colind = nullptr;
+  double *own_val = nullptr;
+  StencilArgs sten{};
+  double *dinv = nullptr;        // Jacobi vector (CSR, VARK)
+  double dconst = 1.0;           // Jacobi constant (constant-diagonal stencils)
+  int prec = SSP_PREC_JACOBI;
+};
+
+namespace {
+
+int fail(ssp_handle *h, int code, const std::string &msg) {
+  if (h) h->err = msg;
+  return code;
+}
+
+#define HIPCHK(h, call)                                                               \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail((h), SSP_EHIP, std::string("HIP error ") + hipGetErrorString(e_) +  \
+                                     " (line " + std::to_string(__LINE__) + ")");     \
+  } while (0)
+
+#define LAUNCHCHK(h) HIPCHK(h, hipGetLastError())
+
+Prec prec_of(const ssp_matrix *A) {
+  if (A->prec == SSP_PREC_NONE) return Prec{nullptr, 1.0};
+  if (A->dinv) return Prec{A->dinv, 0.0};
+  return Prec{nullptr, A->dconst};
+}
+
+int grid_rows(int64_t n) {
+  int64_t g = (n + kWG - 1) / kWG;
+  if (g > kGridMax) g = kGridMax;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+int grid_of(const ssp_matrix *A) {
+  if (A->kind == 0 && A->csr.variant == CSR_STAGED) {
+    int64_t g = A->csr.nrb;
+    if (g > kGridMax) g = kGridMax;
+    return (int)std::max<int64_t>(g, 1);
+  }
+  return grid_rows(A->n);
+}
+
+// profiling: event pairs around launches, by class (0 matrix powers j < s and plain
+// SpMV, 1 last power with moments and s x s solve, 2 vector/block updates, 3 other)
+void prof_begin(ssp_handle *h, int cls) {
+  if (!h->prof_on) return;
+  if (h->ev_used + 2 > h->ev.size()) {
+    for (int i = 0; i < 64; ++i) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return;
+      h->ev.push_back(e);
+    }
+    h->ev_cls.resize(h->ev.size() / 2 + 64);
+  }
+  h->ev_cls[h->ev_used / 2] = cls;
+  (void)hipEventRecord(h->ev[h->ev_used], h->stream);
+}
+void prof_end(ssp_handle *h) {
+  if (!h->prof_on || h->ev_used + 2 > h->ev.size()) return;
+  (void)hipEventRecord(h->ev[h->ev_used + 1], h->stream);
+  h->ev_used += 2;
+}
+void prof_collect(ssp_handle *h) {
+  if (!h->prof_on) return;
+  for (size_t i = 0; i + 1 < h->ev_used; i += 2) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, h->ev[i], h->ev[i + 1]) == hipSuccess) {
+      const int c = h->ev_cls[i / 2];
+      h->prof_launch[c] += 1;
+      h->prof_ms[c] += ms;
+    }
+  }
+  h->ev_used = 0;
+}
+
+template <class Epi>
+int launch_op(ssp_handle *h, const ssp_matrix *A, const double *x, const Epi &epi, int cls) {
+  const int G = grid_of(A);
+  prof_begin(h, cls);
+  switch (A->kind) {
+    case 0:
+      k_csr<Epi><<<G, kWG, 0, h->stream>>>(A->csr, x, epi, h->st, h->ws.partials);
+      break;
+    case SSP_STENCIL_2D5:
+      k_stencil<K_2D5, Epi><<<G, kWG, 0, h->stream>>>(A->sten, x, epi, h->st, h->ws.partials);
+      break;
+    case SSP_STENCIL_3D7:
+      k_stencil<K_3D7, Epi><<<G, kWG, 0, h->stream>>>(A->sten, x, epi, h->st, h->ws.partials);
+      break;
+    case SSP_STENCIL_3D27:
+      k_stencil<K_3D27, Epi><<<G, kWG, 0, h->stream>>>(A->sten, x, epi, h->st, h->ws.partials);
+      break;
+    case SSP_STENCIL_3D7_VARK:
+      k_stencil<K_VARK, Epi><<<G, kWG, 0, h->stream>>>(A->sten, x, epi, h->st, h->ws.partials);
+      break;
+    default:
+      return fail(h, SSP_EINVAL, "unknown operator kind " + std::to_string(A->kind));
+  }
+  if constexpr (Epi::NP > 0) {
+    k_finalize<Epi><<<1, kWG, 0, h->stream>>>(epi, h->st, h->ws.partials, G);
+  }
+  prof_end(h);
+  LAUNCHCHK(h);
+  return SSP_OK;
+}
+
+void hfree(void *&p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+int ensure_workspace(ssp_handle *h, int64_t n, int s, int hist_need, bool pcg) {
+  Workspace &w = h->ws;
+  if (!w.partials) {
+    HIPCHK(h, hipMalloc(&w.partials, sizeof(double) * kGridMax * 2 * kSMax));
+  }
+  if (n > w.n || s > w.s) {
+    hfree((void *&)w.P1);
+    hfree((void *&)w.P2);
+    hfree((void *&)w.r);
+    hfree((void *&)w.pcg_p);
+    hfree((void *&)w.pcg_s);
+    const int64_t nn = std::max(n, w.n);
+    const int ss = std::max(s, w.s);
+    const int64_t ld = (nn + 31) / 32 * 32;  // 256-byte column alignment
+    if (hipMalloc(&w.P1, sizeof(double) * ld * 2 * ss) != hipSuccess ||
+        hipMalloc(&w.P2, sizeof(double) * ld * 2 * ss) != hipSuccess ||
+        hipMalloc(&w.r, sizeof(double) * ld) != hipSuccess) {
+      (void)hipGetLastError();
+      hfree((void *&)w.P1);
+      hfree((void *&)w.P2);
+      hfree((void *&)w.r);
+      w.n = w.s = 0;
+      return fail(h, SSP_ENOMEM, "workspace allocation failed (n=" + std::to_string(n) + ")");
+    }
+    w.n = nn;
+    w.s = ss;
+    w.ld = ld;
+  }
+  if (pcg && !w.pcg_p) {
+    if (hipMalloc(&w.pcg_p, sizeof(double) * w.ld) != hipSuccess ||
+        hipMalloc(&w.pcg_s, sizeof(double) * w.ld) != hipSuccess) {
+      (void)hipGetLastError();
+      hfree((void *&)w.pcg_p);
+      hfree((void *&)w.pcg_s);
+      return fail(h, SSP_ENOMEM, "workspace allocation failed (n=" + std::to_string(n) + ")");
+    }
+  }
+  if (hist_need > w.hist_cap) {
+    hfree((void *&)w.hist);
+    const int cap = std::max(hist_need, 1024);
+    if (hipMalloc(&w.hist, sizeof(double) * cap) != hipSuccess) {
+      (void)hipGetLastError();
+      w.hist_cap = 0;
+      return fail(h, SSP_ENOMEM, "history allocation failed");
+    }
+    w.hist_cap = cap;
+  }
+  return SSP_OK;
+}
+
+// Writes the header of the device control block (status, counters, options).
+int state_init(ssp_handle *h, int s, int outer_max, int fixed, double rtol) {
+  DevState *c = h->h_init;
+  HIPCHK(h, hipStreamSynchronize(h->stream));  // staging buffer reuse
+  memset(c, 0, offsetof(DevState, vm));
+  c->status = ST_RUNNING;
+  c->k = 0;
+  c->outer_max = outer_max;
+  c->fixed = fixed;
+  c->s = s;
+  c->hist_cap = h->ws.hist_cap;
+  c->rtol = rtol;
+  HIPCHK(h, hipMemcpyAsync(h->st, c, offsetof(DevState, vm), hipMemcpyHostToDevice, h->stream));
+  return SSP_OK;
+}
+
+int read_state(ssp_handle *h, bool whole) {
+  const size_t bytes = whole ? sizeof(DevState) : offsetof(DevState, vm);
+  HIPCHK(h, hipMemcpyAsync(h->h_read, h->st, bytes, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return SSP_OK;
+}
+
+// One outer iteration of the s-step method: s matrix-power launches (the last
+// one fused with the moments and the s x s solve) and the fused update.
+template <int S>
+int sstep_iteration(ssp_handle *h, const ssp_matrix *A, double *x, int k) {
+  Workspace &w = h->ws;
+  double *Pc = (k % 2 == 0) ? w.P2 : w.P1;   // Alg. 3: even k fills P2, odd k fills P1
+  double *Po = (k % 2 == 0) ? w.P1 : w.P2;
+  const Prec pc = prec_of(A);
+  for (int j = 1; j <= S; ++j) {
+    const double *zin = Pc + (int64_t)(j - 1) * w.ld;
+    double *az = Pc + (int64_t)(S + j - 1) * w.ld;
+    int rc;
+    if (j < S) {
+      rc = launch_op(h, A, zin, EpiMpk{az, Pc + (int64_t)j * w.ld, pc}, 0);
+    } else {
+      rc = launch_op(h, A, zin, EpiMpkLast<S>{az, Pc, w.ld, w.r, 1}, 1);
+    }
+    if (rc) return rc;
+  }
+  const int G = grid_rows(A->n);
+  prof_begin(h, 2);
+  k_update<S><<<G, kWG, 0, h->stream>>>(A->n, w.ld, Pc, Po, x, w.r, pc, h->st, w.partials);
+  k_finalize<FinUpdate><<<1, kWG, 0, h->stream>>>(FinUpdate{w.hist}, h->st, w.partials, G);
+  prof_end(h);
+  LAUNCHCHK(h);
+  return SSP_OK;
+}
+
+typedef int (*iter_fn)(ssp_handle *, const ssp_matrix *, double *, int);
+
+template <int S>
+int mpk_only(ssp_handle *h, const ssp_matrix *A, const double *r, double *P, int64_t ld) {
+  const Prec pc = prec_of(A);
+  const int G = grid_rows(A->n);
+  k_prec<<<G, kWG, 0, h->stream>>>(A->n, r, P, pc);
+  LAUNCHCHK(h);
+  for (int j = 1; j <= S; ++j) {
+    const double *zin = P + (int64_t)(j - 1) * ld;
+    double *az = P + (int64_t)(S + j - 1) * ld;
+    int rc;
+    if (j < S) rc = launch_op(h, A, zin, EpiMpk{az, P + (int64_t)j * ld, pc}, 0);
+    else rc = launch_op(h, A, zin, EpiMpkLast<S>{az, P, ld, r, 0}, 1);
+    if (rc) return rc;
+  }
+  return SSP_OK;
+}
+
+typedef int (*mpk_fn)(ssp_handle *, const ssp_matrix *, const double *, double *, int64_t);
+
+template <int... Ss>
+struct Dispatch {
+  static iter_fn iter(int s) {
+    iter_fn f = nullptr;
+    ((s == Ss ? (f = &sstep_iteration<Ss>, 0) : 0), ...);
+    return f;
+  }
+  static mpk_fn mpk(int s) {
+    mpk_fn f = nullptr;
+    ((s == Ss ? (f = &mpk_only<Ss>, 0) : 0), ...);
+    return f;
+  }
+};
+using SDispatch = Dispatch<1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16>;
+
+int check_matrix(ssp_handle *h, const ssp_matrix *A) {
+  if (!A || A->h != h) return fail(h, SSP_EINVAL, "matrix is NULL or belongs to another handle");
+  return SSP_OK;
+}
+
+int finish_solve(ssp_handle *h, const ssp_matrix *A, const double *b, double *x, int s,
+                 int outer_max) {
+  // status and the true residual of the returned iterate
+  int rc = read_state(h, false);
+  if (rc) return rc;
+  const int status = h->h_read->status;
+  if (status == ST_ZERO_RHS) HIPCHK(h, hipMemsetAsync(x, 0, sizeof(double) * A->n, h->stream));
+  rc = launch_op(h, A, x, EpiTrueRes{b}, 3);
+  if (rc) return rc;
+  rc = read_state(h, true);
+  if (rc) return rc;
+  prof_collect(h);
+  const DevState &d = *h->h_read;
+  h->last_s = s;
+  h->last_outer = (status == ST_ZERO_RHS) ? 0 : d.k;
+  const double bn = std::sqrt(d.bb);
+  h->last_true_rel = (status == ST_ZERO_RHS || bn == 0.0) ? 0.0 : std::sqrt(d.true_rr) / bn;
+  const int len = std::min(h->last_outer + 1, h->ws.hist_cap);
+  h->last_hist.assign(len, 0.0);
+  if (status != ST_ZERO_RHS && len > 0) {
+    HIPCHK(h, hipMemcpy(h->last_hist.data(), h->ws.hist, sizeof(double) * len,
+                        hipMemcpyDeviceToHost));
+  }
+  (void)outer_max;
+  switch (status) {
+    case ST_CONVERGED:
+    case ST_ZERO_RHS:
+      return SSP_OK;
+    case ST_BREAKDOWN:
+      return SSP_BREAKDOWN;
+    default:
+      return SSP_NOT_CONVERGED;
+  }
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+extern "C" {
+
+int ssp_create(ssp_handle **out, int device, void *stream) {
+  if (!out) return SSP_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+    (void)hipGetLastError();
+    return SSP_EINVAL;
+  }
+  ssp_handle *h = new (std::nothrow) ssp_handle();
+  if (!h) return SSP_ENOMEM;
+  h->device = device;
+  h->stream = (hipStream_t)stream;
+  if (hipSetDevice(device) != hipSuccess || hipMalloc(&h->st, sizeof(DevState)) != hipSuccess ||
+      hipMemset(h->st, 0, sizeof(DevState)) != hipSuccess ||
+      hipHostMalloc((void **)&h->h_init, sizeof(DevState), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void **)&h->h_read, sizeof(DevState), hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    ssp_destroy(h);
+    return SSP_EHIP;
+  }
+  *out = h;
+  return SSP_OK;
+}
+
+int ssp_destroy(ssp_handle *h) {
+  if (!h) return SSP_OK;
+  (void)hipSetDevice(h->device);
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  else (void)hipDeviceSynchronize();
+  Workspace &w = h->ws;
+  hfree((void *&)w.P1);
+  hfree((void *&)w.P2);
+  hfree((void *&)w.r);
+  hfree((void *&)w.pcg_p);
+  hfree((void *&)w.pcg_s);
+  hfree((void *&)w.partials);
+  hfree((void *&)w.hist);
+  hfree((void *&)h->st);
+  if (h->h_init) (void)hipHostFree(h->h_init);
+  if (h->h_read) (void)hipHostFree(h->h_read);
+  for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+  delete h;
+  return SSP_OK;
+}
+
+const char *ssp_last_error(const ssp_handle *h) {
+  static const char none[] = "";
+  return h ? h->err.c_str() : none;
+}
+
+const char *ssp_status_string(int status) {
+  switch (status) {
+    case SSP_OK: return "converged";
+    case SSP_NOT_CONVERGED: return "iteration limit reached before convergence";
+    case SSP_BREAKDOWN: return "breakdown (non-SPD moment matrix, alpha(s) ~ 0 or non-finite value)";
+    case SSP_EINVAL: return "invalid argument";
+    case SSP_ENOMEM: return "out of device memory";
+    case SSP_EHIP: return "HIP runtime error";
+    case SSP_EUNSUPPORTED: return "unsupported combination";
+    default: return "unknown status";
+  }
+}
+
+// Both CSR kernels give bitwise-identical products; pick the faster one for
+// this matrix by timing a few products (SSP_CSR_VARIANT=0/1 forces one).
+static int csr_pick_variant(ssp_handle *h, ssp_matrix *A) {
+  const char *env = getenv("SSP_CSR_VARIANT");
+  if (env && (env[0] == '0' || env[0] == '1')) {
+    A->csr.variant = env[0] - '0';
+    return SSP_OK;
+  }
+  A->csr.variant = CSR_STAGED;
+  h->prof_on = false;
+  int rc = ensure_workspace(h, 1, 1, 1, false);
+  if (rc) return rc;
+  double *y = nullptr;
+  HIPCHK(h, hipMalloc(&y, sizeof(double) * A->n));
+  hipEvent_t e0, e1;
+  HIPCHK(h, hipEventCreate(&e0));
+  HIPCHK(h, hipEventCreate(&e1));
+  float best = 1e30f;
+  int best_v = CSR_STAGED;
+  for (int v = CSR_STAGED; v <= CSR_ROW; ++v) {
+    A->csr.variant = v;
+    rc = launch_op(h, A, A->dinv, EpiStore{y}, 0);  // warm-up
+    if (rc) break;
+    (void)hipEventRecord(e0, h->stream);
+    for (int t = 0; t < 3; ++t) launch_op(h, A, A->dinv, EpiStore{y}, 0);
+    (void)hipEventRecord(e1, h->stream);
+    (void)hipEventSynchronize(e1);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms < best) {
+      best = ms;
+      best_v = v;
+    }
+  }
+  A->csr.variant = best_v;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(y);
+  return rc;
+}
+
+static int csr_finish_setup(ssp_handle *h, ssp_matrix *A) {
+  // longest row -> rows per LDS block; Jacobi vector
+  int *d_max = nullptr;
+  HIPCHK(h, hipMalloc(&d_max, sizeof(int)));
+  HIPCHK(h, hipMemsetAsync(d_max, 0, sizeof(int), h->stream));
+  const int64_t nb = (A->n + kWG - 1) / kWG;
+  k_csr_maxrow<<<(unsigned)nb, kWG, 0, h->stream>>>(A->n, A->csr.rowptr, d_max);
+  LAUNCHCHK(h);
+  int maxrow = 0;
+  HIPCHK(h, hipMemcpyAsync(&maxrow, d_max, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  (void)hipFree(d_max);
+  // as many rows per LDS block as fit (the longest row decides)
+  int R = maxrow > 0 ? kCsrLds / maxrow : kCsrRowsMax;
+  if (R > kCsrRowsMax) R = kCsrRowsMax;
+  if (R < 1) R = 1;
+  A->csr.rows_per_rb = R;
+  A->csr.nrb = (A->n + R - 1) / R;
+  HIPCHK(h, hipMalloc(&A->dinv, sizeof(double) * A->n));
+  k_csr_dinv<<<(unsigned)nb, kWG, 0, h->stream>>>(A->n, A->csr.rowptr, A->csr.colind,
+                                                  A->csr.val, A->dinv);
+  LAUNCHCHK(h);
+  return csr_pick_variant(h, A);
+}
+
+int ssp_matrix_csr(ssp_handle *h, int64_t n, int64_t nnz, const int32_t *rowptr,
+                   const int32_t *colind, const double *val, unsigned flags, ssp_matrix **out) {
+  if (!h || !out) return SSP_EINVAL;
+  *out = nullptr;
+  if (n < 1 || nnz < n || nnz >= (int64_t)1 << 31 || !rowptr || !colind || !val)
+    return fail(h, SSP_EINVAL, "ssp_matrix_csr: invalid sizes or pointers (n=" + std::to_string(n) + ")");
+  HIPCHK(h, hipSetDevice(h->device));
+  ssp_matrix *A = new (std::nothrow) ssp_matrix();
+  if (!A) return SSP_ENOMEM;
+  A->h = h;
+  A->kind = 0;
+  A->n = n;
+  A->nnz = nnz;
+  if (flags & SSP_COPY) {
+    if (hipMalloc(&A->own_rowptr, sizeof(int32_t) * (n + 1)) != hipSuccess ||
+        hipMalloc(&A->own_colind, sizeof(int32_t) * nnz) != hipSuccess ||
+        hipMalloc(&A->own_val, sizeof(double) * nnz) != hipSuccess) {
+      (void)hipGetLastError();
+      ssp_matrix_destroy(A);
+      return fail(h, SSP_ENOMEM, "ssp_matrix_csr: copy allocation failed");
+    }
+    (void)hipMemcpyAsync(A->own_rowptr, rowptr, sizeof(int32_t) * (n + 1),
+                         hipMemcpyDeviceToDevice, h->stream);
+    (void)hipMemcpyAsync(A->own_colind, colind, sizeof(int32_t) * nnz, hipMemcpyDeviceToDevice,
+                         h->stream);
+    (void)hipMemcpyAsync(A->own_val, val, sizeof(double) * nnz, hipMemcpyDeviceToDevice,
+                         h->stream);
+    rowptr = A->own_rowptr;
+    colind = A->own_colind;
+    val = A->own_val;
+  }
+  A->csr.n = n;
+  A->csr.rowptr = rowptr;
+  A->csr.colind = colind;
+  A->csr.val = val;
+  if (flags & SSP_VALIDATE) {
+    int *d_bad = nullptr;
+    int bad = 0;
+    if (hipMalloc(&d_bad, sizeof(int)) != hipSuccess) {
+      ssp_matrix_destroy(A);
+      return fail(h, SSP_ENOMEM, "validation flag allocation failed");
+    }
+    (void)hipMemsetAsync(d_bad, 0, sizeof(int), h->stream);
+    k_csr_validate<<<(unsigned)((n + kWG - 1) / kWG), kWG, 0, h->stream>>>(n, nnz, rowptr, colind,
+                                                                           val, d_bad);
+    (void)hipMemcpyAsync(&bad, d_bad, sizeof(int), hipMemcpyDeviceToHost, h->stream);
+    (void)hipStreamSynchronize(h->stream);
+    (void)hipFree(d_bad);
+    if (bad) {
+      ssp_matrix_destroy(A);
+      return fail(h, SSP_EINVAL, "ssp_matrix_csr: validation failed");
+    }
+  }
+  int rc = csr_finish_setup(h, A);
+  if (rc) {
+    ssp_matrix_destroy(A);
+    return rc;
+  }
+  *out = A;
+  return SSP_OK;
+}
+
+static int stencil_args(ssp_handle *h, int kind, int nx, int ny, int nz, const double *coef,
+                        ssp_matrix *A) {
+  if (nx < 1 || ny < 1 || nz < 1 || (kind == SSP_STENCIL_2D5 && nz != 1) ||
+      kind < SSP_STENCIL_2D5 || kind > SSP_STENCIL_3D7_VARK)
+    return fail(h, SSP_EINVAL, "invalid stencil kind or grid (kind=" + std::to_string(kind) + ")");
+  const int64_t n = (int64_t)nx * ny * nz;
+  if (n >= (int64_t)1 << 31) return fail(h, SSP_EINVAL, "grid too large (n=" + std::to_string(n) + ")");
+  StencilArgs &S = A->sten;
+  S.n = n;
+  S.nx = nx;
+  S.ny = ny;
+  S.nz = nz;
+  S.fx = FastDiv{nx, 1.0 / nx};
+  S.fy = FastDiv{ny, 1.0 / ny};
+  S.k = nullptr;
+  A->n = n;
+  if (kind == SSP_STENCIL_3D7_VARK) {
+    if (!coef) return fail(h, SSP_EINVAL, "3D7_VARK needs the device coefficient array");
+    S.k = coef;
+    S.diag = S.off = 0.0;
+  } else {
+    const double dflt[4][2] = {{0, 0}, {4.0, -1.0}, {6.0, -1.0}, {26.0, -1.0}};
+    S.diag = coef ? coef[0] : dflt[kind][0];
+    S.off = coef ? coef[1] : dflt[kind][1];
+  }
+  const int64_t m = (kind == SSP_STENCIL_3D27) ? (int64_t)(3 * nx - 2) * (3 * ny - 2) * (3 * nz - 2)
+                    : (kind == SSP_STENCIL_2D5)
+                        ? 5LL * nx * ny - 2LL * nx - 2LL * ny
+                        : 7LL * nx * ny * nz - 2LL * nx * ny - 2LL * ny * nz - 2LL * nx * nz;
+  A->nnz = m;
+  return SSP_OK;
+}
+
+int ssp_matrix_stencil(ssp_handle *h, int kind, int nx, int ny, int nz, const double *coef,
+                       ssp_matrix **out) {
+  if (!h || !out) return SSP_EINVAL;
+  *out = nullptr;
+  HIPCHK(h, hipSetDevice(h->device));
+  ssp_matrix *A = new (std::nothrow) ssp_matrix();
+  if (!A) return SSP_ENOMEM;
+  A->h = h;
+  A->kind = kind;
+  int rc = stencil_args(h, kind, nx, ny, nz, coef, A);
+  if (rc) {
+    delete A;
+    return rc;
+  }
+  if (kind == SSP_STENCIL_3D7_VARK) {
+    if (hipMalloc(&A->dinv, sizeof(double) * A->n) != hipSuccess) {
+      (void)hipGetLastError();
+      delete A;
+      return fail(h, SSP_ENOMEM, "Jacobi vector allocation failed");
+    }
+    k_vark_dinv<<<(unsigned)((A->n + kWG - 1) / kWG), kWG, 0, h->stream>>>(A->sten, A->dinv);
+    LAUNCHCHK(h);
+  } else {
+    A->dconst = 1.0 / A->sten.diag;
+  }
+  *out = A;
+  return SSP_OK;
+}
+
+int ssp_matrix_csr_from_stencil(ssp_handle *h, int kind, int nx, int ny, int nz,
+                                const double *coef, ssp_matrix **out) {
+  if (!h || !out) return SSP_EINVAL;
+  *out = nullptr;
+  HIPCHK(h, hipSetDevice(h->device));
+  ssp_matrix tmp;
+  int rc = stencil_args(h, kind, nx, ny, nz, coef, &tmp);
+  if (rc) return rc;
+  const int64_t n = tmp.n;
+  // row pointer on the host from the row lengths of the grid (setup only)
+  std::vector<int32_t> rp(n + 1);
+  rp[0] = 0;
+  int64_t e = 0, p = 0;
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x, ++p) {
+        const int cx = 1 + (x > 0) + (x < nx - 1);
+        const int cy = 1 + (y > 0) + (y < ny - 1);
+        const int cz = (kind == SSP_STENCIL_2D5) ? 1 : 1 + (z > 0) + (z < nz - 1);
+        e += (kind == SSP_STENCIL_3D27) ? cx * cy * cz : 1 + (cx - 1) + (cy - 1) + (cz - 1);
+        if (e >= ((int64_t)1 << 31)) return fail(h, SSP_EINVAL, "nnz exceeds int32 indexing");
+        rp[p + 1] = (int32_t)e;
+      }
+  ssp_matrix *A = new (std::nothrow) ssp_matrix();
+  if (!A) return SSP_ENOMEM;
+  A->h = h;
+  A->kind = 0;
+  A->n = n;
+  A->nnz = e;
+  if (hipMalloc(&A->own_rowptr, sizeof(int32_t) * (n + 1)) != hipSuccess ||
+      hipMalloc(&A->own_colind, sizeof(int32_t) * e) != hipSuccess ||
+      hipMalloc(&A->own_val, sizeof(double) * e) != hipSuccess) {
+    (void)hipGetLastError();
+    ssp_matrix_destroy(A);
+    return fail(h, SSP_ENOMEM, "CSR allocation failed (nnz=" + std::to_string(e) + ")");
+  }
+  HIPCHK(h, hipMemcpy(A->own_rowptr, rp.data(), sizeof(int32_t) * (n + 1),
+                      hipMemcpyHostToDevice));
+  const unsigned nb = (unsigned)((n + kWG - 1) / kWG);
+  switch (kind) {
+    case SSP_STENCIL_2D5:
+      k_stencil_fill<K_2D5><<<nb, kWG, 0, h->stream>>>(tmp.sten, A->own_rowptr, A->own_colind, A->own_val);
+      break;
+    case SSP_STENCIL_3D7:
+      k_stencil_fill<K_3D7><<<nb, kWG, 0, h->stream>>>(tmp.sten, A->own_rowptr, A->own_colind, A->own_val);
+      break;
+    case SSP_STENCIL_3D27:
+      k_stencil_fill<K_3D27><<<nb, kWG, 0, h->stream>>>(tmp.sten, A->own_rowptr, A->own_colind, A->own_val);
+      break;
+    default:
+      k_stencil_fill<K_VARK><<<nb, kWG, 0, h->stream>>>(tmp.sten, A->own_rowptr, A->own_colind, A->own_val);
+      break;
+  }
+  LAUNCHCHK(h);
+  A->csr.n = n;
+  A->csr.rowptr = A->own_rowptr;
+  A->csr.colind = A->own_colind;
+  A->csr.val = A->own_val;
+  rc = csr_finish_setup(h, A);
+  if (rc) {
+    ssp_matrix_destroy(A);
+    return rc;
+  }
+  *out = A;
+  return SSP_OK;
+}
+
+int ssp_matrix_info(const ssp_matrix *A, int64_t *n, int64_t *nnz) {
+  if (!A) return SSP_EINVAL;
+  if (n) *n = A->n;
+  if (nnz) *nnz = A->nnz;
+  return SSP_OK;
+}
+
+int ssp_matrix_csr_arrays(const ssp_matrix *A, const int32_t **rowptr, const int32_t **colind,
+                          const double **val) {
+  if (!A || A->kind != 0) return SSP_EINVAL;
+  if (rowptr) *rowptr = A->csr.rowptr;
+  if (colind) *colind = A->csr.colind;
+  if (val) *val = A->csr.val;
+  return SSP_OK;
+}
+
+int ssp_matrix_destroy(ssp_matrix *A) {
+  if (!A) return SSP_OK;
+  if (A->h) {
+    (void)hipSetDevice(A->h->device);
+    (void)hipStreamSynchronize(A->h->stream);
+  }
+  hfree((void *&)A->own_rowptr);
+  hfree((void *&)A->own_colind);
+  hfree((void *&)A->own_val);
+  hfree((void *&)A->dinv);
+  delete A;
+  return SSP_OK;
+}
+
+int ssp_set_preconditioner(ssp_matrix *A, int kind) {
+  if (!A || (kind != SSP_PREC_NONE && kind != SSP_PREC_JACOBI)) return SSP_EINVAL;
+  A->prec = kind;
+  return SSP_OK;
+}
+
+int ssp_spmv(ssp_handle *h, const ssp_matrix *A, const double *x, double *y) {
+  if (!h) return SSP_EINVAL;
+  int rc = check_matrix(h, A);
+  if (rc) return rc;
+  if (!x || !y) return fail(h, SSP_EINVAL, "ssp_spmv: NULL vector");
+  HIPCHK(h, hipSetDevice(h->device));
+  rc = ensure_workspace(h, 1, 1, 1, false);
+  if (rc) return rc;
+  return launch_op(h, A, x, EpiStore{y}, 0);
+}
+
+int ssp_mpk(ssp_handle *h, const ssp_matrix *A, const double *r, int s, double *P, int64_t ld,
+            double *vm) {
+  if (!h) return SSP_EINVAL;
+  int rc = check_matrix(h, A);
+  if (rc) return rc;
+  if (!r || !P || s < 1 || s > SSP_SMAX || s > A->n || ld < A->n)
+    return fail(h, SSP_EINVAL, "ssp_mpk: invalid arguments (s=" + std::to_string(s) + ")");
+  HIPCHK(h, hipSetDevice(h->device));
+  rc = ensure_workspace(h, 1, 1, 1, false);
+  if (rc) return rc;
+  rc = state_init(h, s, 1, 1, 0.0);
+  if (rc) return rc;
+  rc = SDispatch::mpk(s)(h, A, r, P, ld);
+  if (rc) return rc;
+  if (vm) {
+    rc = read_state(h, true);
+    if (rc) return rc;
+    memcpy(vm, h->h_read->vm, sizeof(double) * 2 * s);
+  }
+  return SSP_OK;
+}
+
+static int solve_sstep(ssp_handle *h, const ssp_matrix *A, const double *b, double *x, int s,
+                       double rtol, int maxit, const ssp_opts *o) {
+  const int fixed = (o && o->fixed_outer > 0) ? o->fixed_outer : 0;
+  const int outer_max = fixed ? fixed : (int)((maxit + (int64_t)s - 1) / s);
+  int rc = ensure_workspace(h, A->n, s, outer_max + 1, false);
+  if (rc) return rc;
+  Workspace &w = h->ws;
+  rc = state_init(h, s, outer_max, fixed ? 1 : 0, rtol);
+  if (rc) return rc;
+  // r = b - A x0 and z1 = B^-1 r into column 1 of the block used at k = 0
+  rc = launch_op(h, A, x, EpiInit{b, w.r, w.P2, prec_of(A), w.hist}, 3);
+  if (rc) return rc;
+  const iter_fn step = SDispatch::iter(s);
+  const int trace_cap = (o && o->trace_cap > 0 && o->trace_vm && o->trace_alpha &&
+                         o->trace_beta && o->trace_W) ? o->trace_cap : 0;
+  int every = (o && o->check_every > 0) ? o->check_every : std::max(1, 32 / s);
+  if (trace_cap) every = 1;
+  int k = 0;
+  rc = read_state(h, false);
+  if (rc) return rc;
+  while (k < outer_max && h->h_read->status == ST_RUNNING) {
+    const int m = std::min(every, outer_max - k);
+    for (int i = 0; i < m; ++i, ++k) {
+      rc = step(h, A, x, k);
+      if (rc) return rc;
+    }
+    rc = read_state(h, trace_cap > 0);
+    if (rc) return rc;
+    if (trace_cap) {
+      const DevState &d = *h->h_read;
+      const int it = d.k - 1;  // iteration whose coefficients are in the block
+      if (d.k == k && it < trace_cap) {
+        memcpy(o->trace_vm + (size_t)it * 2 * s, d.vm, sizeof(double) * 2 * s);
+        memcpy(o->trace_alpha + (size_t)it * s, d.alpha, sizeof(double) * s);
+        memcpy(o->trace_beta + (size_t)it * s * s, d.beta, sizeof(double) * s * s);
+        memcpy(o->trace_W + (size_t)it * s * s, d.W, sizeof(double) * s * s);
+      }
+    }
+  }
+  return finish_solve(h, A, b, x, s, outer_max);
+}
+
+static int solve_pcg(ssp_handle *h, const ssp_matrix *A, const double *b, double *x,
+                     double rtol, int maxit, const ssp_opts *o) {
+  const int fixed = (o && o->fixed_outer > 0) ? o->fixed_outer : 0;
+  const int outer_max = fixed ? fixed : maxit;
+  int rc = ensure_workspace(h, A->n, 1, outer_max + 1, true);
+  if (rc) return rc;
+  Workspace &w = h->ws;
+  rc = state_init(h, 1, outer_max, fixed ? 1 : 0, rtol);
+  if (rc) return rc;
+  const Prec pc = prec_of(A);
+  rc = launch_op(h, A, x, EpiPcgInit{b, w.r, w.pcg_p, pc, w.hist}, 3);
+  if (rc) return rc;
+  const int every = (o && o->check_every > 0) ? o->check_every : 32;
+  const int G = grid_rows(A->n);
+  int k = 0;
+  rc = read_state(h, false);
+  if (rc) return rc;
+  while (k < outer_max && h->h_read->status == ST_RUNNING) {
+    const int m = std::min(every, outer_max - k);
+    for (int i = 0; i < m; ++i, ++k) {
+      rc = launch_op(h, A, w.pcg_p, EpiPcgSpmv{w.pcg_p, w.pcg_s}, 0);
+      if (rc) return rc;
+      prof_begin(h, 2);
+      k_pcg_update<<<G, kWG, 0, h->stream>>>(A->n, x, w.r, w.pcg_p, w.pcg_s, pc, h->st,
+                                             w.partials);
+      k_finalize<FinPcgUpdate><<<1, kWG, 0, h->stream>>>(FinPcgUpdate{w.hist}, h->st, w.partials,
+                                                         G);
+      prof_end(h);
+      LAUNCHCHK(h);
+      prof_begin(h, 2);
+      k_pcg_direction<<<G, kWG, 0, h->stream>>>(A->n, w.r, w.pcg_p, pc, h->st);
+      prof_end(h);
+      LAUNCHCHK(h);
+    }
+    rc = read_state(h, false);
+    if (rc) return rc;
+  }
+  return finish_solve(h, A, b, x, 1, outer_max);
+}
+
+int ssp_solve(ssp_handle *h, const ssp_matrix *A, const double *b, double *x, int s, double rtol,
+              int maxit, const ssp_opts *opts) {
+  if (!h) return SSP_EINVAL;
+  int rc = check_matrix(h, A);
+  if (rc) return rc;
+  const int method = opts ? opts->method : SSP_METHOD_SSTEP;
+  if (!b || !x) return fail(h, SSP_EINVAL, "ssp_solve: NULL vector");
+  if (!(rtol >= 0.0) || maxit < 0) return fail(h, SSP_EINVAL, "ssp_solve: rtol must be >= 0 and maxit >= 0");
+  if (method == SSP_METHOD_SSTEP && (s < 1 || s > SSP_SMAX || s > A->n))
+    return fail(h, SSP_EINVAL, "ssp_solve: s out of range (s=" + std::to_string(s) + ")");
+  if (method != SSP_METHOD_SSTEP && method != SSP_METHOD_PCG)
+    return fail(h, SSP_EINVAL, "ssp_solve: unknown method " + std::to_string(method));
+  if (opts && opts->precision != SSP_PRECISION_FP64)
+    return fail(h, SSP_EUNSUPPORTED, "ssp_solve: precision " + std::to_string(opts->precision) + " not available");
+  HIPCHK(h, hipSetDevice(h->device));
+  h->prof_on = opts && opts->profile;
+  h->ev_used = 0;
+  for (int c = 0; c < 4; ++c) {
+    h->prof_launch[c] = 0;
+    h->prof_ms[c] = 0.0;
+  }
+  if (method == SSP_METHOD_PCG) return solve_pcg(h, A, b, x, rtol, maxit, opts);
+  return solve_sstep(h, A, b, x, s, rtol, maxit, opts);
+}
+
+int ssp_get_iterations(const ssp_handle *h, int *outer, int *cg_equiv) {
+  if (!h) return SSP_EINVAL;
+  if (outer) *outer = h->last_outer;
+  if (cg_equiv) *cg_equiv = h->last_outer * h->last_s;
+  return SSP_OK;
+}
+
+int ssp_get_residual_history(const ssp_handle *h, double *buf, int cap, int *len) {
+  if (!h || cap < 0 || (cap > 0 && !buf)) return SSP_EINVAL;
+  const int n = (int)h->last_hist.size();
+  for (int i = 0; i < std::min(n, cap); ++i) buf[i] = h->last_hist[i];
+  if (len) *len = n;
+  return SSP_OK;
+}
+
+int ssp_get_true_residual(const ssp_handle *h, double *rel) {
+  if (!h || !rel) return SSP_EINVAL;
+  *rel = h->last_true_rel;
+  return SSP_OK;
+}
+
+int ssp_get_profile(const ssp_handle *h, int *launches, double *ms) {
+  if (!h) return SSP_EINVAL;
+  for (int c = 0; c < 4; ++c) {
+    if (launches) launches[c] = h->prof_launch[c];
+    if (ms) ms[c] = h->prof_ms[c];
+  }
+  return SSP_OK;
+}
+
+}  // extern "C"

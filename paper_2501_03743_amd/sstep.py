@@ -1,0 +1,345 @@
+"""Thin ctypes binding of libsstep.so (include/sstep.h).
+
+Argument marshalling only: torch tensors supply device memory and the
+stream, and every step of a solve runs in the library's HIP kernels.  There
+is no fallback: if the library is missing or no GPU is present, the calls
+raise.
+"""
+from __future__ import annotations
+
+import atexit
+import ctypes as C
+import os
+import weakref
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsstep.so")
+
+OK, NOT_CONVERGED, BREAKDOWN = 0, 1, 2
+EINVAL, ENOMEM, EHIP, EUNSUPPORTED = -1, -2, -3, -4
+SMAX = 16
+STENCIL = {"2d5": 1, "3d7": 2, "3d27": 3, "3d7_vark": 4}
+BORROW, COPY, VALIDATE = 0, 1, 2
+PREC = {"none": 0, "jacobi": 1}
+METHOD = {"sstep": 0, "pcg": 1}
+PRECISION = {"fp64": 0, "mixed_ir": 1}
+
+# C symbols declared in include/sstep.h (checked by the CPU tests)
+EXPORTS = (
+    "ssp_create", "ssp_destroy", "ssp_matrix_csr", "ssp_matrix_stencil",
+    "ssp_matrix_csr_from_stencil", "ssp_matrix_info", "ssp_matrix_csr_arrays",
+    "ssp_matrix_destroy", "ssp_set_preconditioner", "ssp_spmv", "ssp_mpk", "ssp_solve",
+    "ssp_get_iterations", "ssp_get_residual_history", "ssp_get_true_residual",
+    "ssp_get_profile", "ssp_status_string", "ssp_last_error",
+)
+
+
+class SspError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (status_string(code), code, msg))
+        self.code = code
+
+
+class _Opts(C.Structure):
+    _fields_ = [("method", C.c_int), ("precision", C.c_int), ("inner_rtol", C.c_double),
+                ("max_refine", C.c_int), ("check_every", C.c_int), ("fixed_outer", C.c_int),
+                ("profile", C.c_int), ("trace_cap", C.c_int),
+                ("trace_vm", C.c_void_p), ("trace_alpha", C.c_void_p),
+                ("trace_beta", C.c_void_p), ("trace_W", C.c_void_p)]
+
+
+_lib = None
+_live_handles = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    # release library objects before the HIP runtime is torn down
+    for h in list(_live_handles):
+        try:
+            h.close()
+        except Exception:
+            pass
+
+
+def load():
+    """Loads libsstep.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libsstep.so is not built: run `python -m paper_2501_03743_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int, C.c_int64, C.c_double
+    sig = {
+        "ssp_create": (i32, [C.POINTER(vp), i32, vp]),
+        "ssp_destroy": (i32, [vp]),
+        "ssp_matrix_csr": (i32, [vp, i64, i64, vp, vp, vp, C.c_uint, C.POINTER(vp)]),
+        "ssp_matrix_stencil": (i32, [vp, i32, i32, i32, i32, vp, C.POINTER(vp)]),
+        "ssp_matrix_csr_from_stencil": (i32, [vp, i32, i32, i32, i32, vp, C.POINTER(vp)]),
+        "ssp_matrix_info": (i32, [vp, C.POINTER(i64), C.POINTER(i64)]),
+        "ssp_matrix_csr_arrays": (i32, [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp)]),
+        "ssp_matrix_destroy": (i32, [vp]),
+        "ssp_set_preconditioner": (i32, [vp, i32]),
+        "ssp_spmv": (i32, [vp, vp, vp, vp]),
+        "ssp_mpk": (i32, [vp, vp, vp, i32, vp, i64, vp]),
+        "ssp_solve": (i32, [vp, vp, vp, vp, i32, dbl, i32, C.POINTER(_Opts)]),
+        "ssp_get_iterations": (i32, [vp, C.POINTER(i32), C.POINTER(i32)]),
+        "ssp_get_residual_history": (i32, [vp, vp, i32, C.POINTER(i32)]),
+        "ssp_get_true_residual": (i32, [vp, C.POINTER(dbl)]),
+        "ssp_get_profile": (i32, [vp, vp, vp]),
+        "ssp_status_string": (C.c_char_p, [i32]),
+        "ssp_last_error": (C.c_char_p, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def status_string(code: int) -> str:
+    return load().ssp_status_string(code).decode()
+
+
+def _ptr(t) -> int:
+    return 0 if t is None else int(t.data_ptr())
+
+
+def _check_dev(t, dtype, n=None, name="tensor"):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if n is not None and t.numel() < n:
+        raise ValueError("%s has %d entries, needs %d" % (name, t.numel(), n))
+
+
+@dataclass
+class SolveResult:
+    status: int
+    outer: int
+    cg_equiv: int
+    true_rel: float
+    hist: np.ndarray
+    trace: Optional[dict] = None
+    profile: Optional[dict] = None
+
+    @property
+    def ok(self):
+        return self.status == OK
+
+
+class Matrix:
+    def __init__(self, handle, ptr, n, nnz, keep):
+        self.handle = handle
+        self._p = ptr
+        self.n = n
+        self.nnz = nnz
+        self._keep = keep       # tensors the library borrows
+        handle._matrices.add(self)
+
+    def set_preconditioner(self, kind: str):
+        rc = load().ssp_set_preconditioner(self._p, PREC[kind])
+        if rc:
+            raise SspError(rc, "set_preconditioner")
+
+    def csr_arrays(self):
+        """(rowptr, colind, val) as torch tensors viewing the library's device arrays."""
+        import torch
+        lib = load()
+        rp, ci, va = C.c_void_p(), C.c_void_p(), C.c_void_p()
+        rc = lib.ssp_matrix_csr_arrays(self._p, C.byref(rp), C.byref(ci), C.byref(va))
+        if rc:
+            raise SspError(rc, "not a CSR matrix")
+        dev = "cuda:%d" % self.handle.device
+        torch.cuda.synchronize()
+        out = []
+        for ptr, cnt, ts in ((rp.value, self.n + 1, "<i4"), (ci.value, self.nnz, "<i4"),
+                             (va.value, self.nnz, "<f8")):
+            view = torch.as_tensor(_DeviceArray(ptr, cnt, ts), device=dev)
+            out.append(view.clone())
+        return tuple(out)
+
+    def close(self):
+        # a matrix must be destroyed before its handle; Handle.close() does it
+        if self._p and self.handle._h:
+            load().ssp_matrix_destroy(self._p)
+        self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _DeviceArray:
+    """Exposes a library-owned device array to torch (zero-copy view)."""
+
+    def __init__(self, ptr, count, typestr):
+        self.__cuda_array_interface__ = {"shape": (count,), "typestr": typestr,
+                                         "data": (ptr, False), "version": 2, "strides": None}
+
+
+class Handle:
+    """A library handle bound to one device and (by default) torch's current stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device: the s-step solver runs only on the GPU")
+        lib = load()
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        self._h = C.c_void_p()
+        self._matrices = weakref.WeakSet()
+        rc = lib.ssp_create(C.byref(self._h), device, C.c_void_p(stream.cuda_stream))
+        if rc:
+            raise SspError(rc, "ssp_create")
+        _live_handles.add(self)
+
+    # ---------------------------------------------------------------- util
+    def _err(self, rc, what):
+        msg = load().ssp_last_error(self._h).decode()
+        raise SspError(rc, "%s: %s" % (what, msg))
+
+    def close(self):
+        if self._h:
+            for m in list(self._matrices):
+                m.close()
+            load().ssp_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- matrices
+    def matrix_csr(self, rowptr, colind, val, flags: int = BORROW) -> Matrix:
+        import torch
+        n = rowptr.numel() - 1
+        nnz = colind.numel()
+        _check_dev(rowptr, torch.int32, name="rowptr")
+        _check_dev(colind, torch.int32, name="colind")
+        _check_dev(val, torch.float64, nnz, name="val")
+        out = C.c_void_p()
+        rc = load().ssp_matrix_csr(self._h, n, nnz, _ptr(rowptr), _ptr(colind), _ptr(val), flags,
+                                   C.byref(out))
+        if rc:
+            self._err(rc, "ssp_matrix_csr")
+        keep = [] if flags & COPY else [rowptr, colind, val]
+        return Matrix(self, out.value, n, nnz, keep)
+
+    def _stencil(self, fn, kind, shape, coef=None, k=None):
+        import torch
+        nx, ny, nz = (tuple(shape) + (1,))[:3] if len(shape) == 2 else tuple(shape)
+        kd = STENCIL[kind]
+        keep = []
+        if kind == "3d7_vark":
+            _check_dev(k, torch.float64, nx * ny * nz, name="k")
+            cptr = C.c_void_p(_ptr(k))
+            keep.append(k)
+        elif coef is not None:
+            carr = (C.c_double * 2)(*coef)
+            cptr = C.cast(carr, C.c_void_p)
+            keep.append(carr)
+        else:
+            cptr = None
+        out = C.c_void_p()
+        rc = fn(self._h, kd, nx, ny, nz, cptr, C.byref(out))
+        if rc:
+            self._err(rc, fn.__name__)
+        n, nnz = C.c_int64(), C.c_int64()
+        load().ssp_matrix_info(out.value, C.byref(n), C.byref(nnz))
+        return Matrix(self, out.value, n.value, nnz.value, keep)
+
+    def matrix_stencil(self, kind: str, shape, coef=None, k=None) -> Matrix:
+        return self._stencil(load().ssp_matrix_stencil, kind, shape, coef, k)
+
+    def matrix_csr_from_stencil(self, kind: str, shape, coef=None, k=None) -> Matrix:
+        return self._stencil(load().ssp_matrix_csr_from_stencil, kind, shape, coef, k)
+
+    # ---------------------------------------------------------------- building blocks
+    def spmv(self, A: Matrix, x, y):
+        import torch
+        _check_dev(x, torch.float64, A.n, "x")
+        _check_dev(y, torch.float64, A.n, "y")
+        rc = load().ssp_spmv(self._h, A._p, _ptr(x), _ptr(y))
+        if rc:
+            self._err(rc, "ssp_spmv")
+
+    def mpk(self, A: Matrix, r, s: int, P=None):
+        """Alg. 4 + Alg. 5: returns (P as a (2s, n) view of the block, vm)."""
+        import torch
+        _check_dev(r, torch.float64, A.n, "r")
+        if P is None:
+            P = torch.empty((2 * s, A.n), dtype=torch.float64, device=r.device)
+        vm = np.zeros(2 * s)
+        rc = load().ssp_mpk(self._h, A._p, _ptr(r), s, _ptr(P), P.stride(0),
+                            vm.ctypes.data_as(C.c_void_p))
+        if rc:
+            self._err(rc, "ssp_mpk")
+        return P, vm
+
+    # ---------------------------------------------------------------- solve
+    def solve(self, A: Matrix, b, x, s: int = 4, rtol: float = 1e-8, maxit: int = 10000,
+              method: str = "sstep", precision: str = "fp64", inner_rtol: float = 1e-5,
+              max_refine: int = 10, check_every: int = 0, fixed_outer: int = 0,
+              profile: bool = False, trace_cap: int = 0) -> SolveResult:
+        import torch
+        _check_dev(b, torch.float64, A.n, "b")
+        _check_dev(x, torch.float64, A.n, "x")
+        o = _Opts(method=METHOD[method], precision=PRECISION[precision], inner_rtol=inner_rtol,
+                  max_refine=max_refine, check_every=check_every, fixed_outer=fixed_outer,
+                  profile=1 if profile else 0, trace_cap=0)
+        trace = None
+        if trace_cap > 0:
+            trace = dict(vm=np.zeros((trace_cap, 2 * s)), alpha=np.zeros((trace_cap, s)),
+                         beta=np.zeros((trace_cap, s, s)), W=np.zeros((trace_cap, s, s)))
+            o.trace_cap = trace_cap
+            o.trace_vm = trace["vm"].ctypes.data
+            o.trace_alpha = trace["alpha"].ctypes.data
+            o.trace_beta = trace["beta"].ctypes.data
+            o.trace_W = trace["W"].ctypes.data
+        lib = load()
+        rc = lib.ssp_solve(self._h, A._p, _ptr(b), _ptr(x), s, rtol, maxit, C.byref(o))
+        if rc < 0:
+            self._err(rc, "ssp_solve")
+        outer, cge = C.c_int(), C.c_int()
+        lib.ssp_get_iterations(self._h, C.byref(outer), C.byref(cge))
+        ln = C.c_int()
+        lib.ssp_get_residual_history(self._h, None, 0, C.byref(ln))
+        hist = np.zeros(ln.value)
+        lib.ssp_get_residual_history(self._h, hist.ctypes.data_as(C.c_void_p), ln.value,
+                                     C.byref(ln))
+        tr = C.c_double()
+        lib.ssp_get_true_residual(self._h, C.byref(tr))
+        prof = None
+        if profile:
+            launches = (C.c_int * 4)()
+            ms = (C.c_double * 4)()
+            lib.ssp_get_profile(self._h, launches, ms)
+            prof = dict(launches=list(launches), ms=list(ms))
+        if trace is not None:
+            trace = {k: v[:outer.value] for k, v in trace.items()}
+        return SolveResult(status=rc, outer=outer.value, cg_equiv=cge.value, true_rel=tr.value,
+                           hist=hist, trace=trace, profile=prof)

@@ -337,3 +337,33 @@ def test_paper_iteration_count_250cubed():
     r = oracle.sstep(op, b, 1, rtol=1e-6, maxit=2000, prec=oracle.PREC_NONE)
     assert r.status == oracle.OK
     assert abs(r.outer - 514) <= 0.03 * 514, r.outer
+
+
+def test_mpk_basis_and_moment_identities():
+    """Alg. 4 fills [z, Kz, .., K^{s-1} z | A z, .., A K^{s-1} z] with z = B^-1 r;
+    Alg. 5's vm(j) are the moments mu_{j-1} = r^T K^{j-1} B^-1 r, and the
+    Gram matrix Z^T A Z is the Hankel matrix (vm(i+j))."""
+    shape = (6, 7, 5)
+    k = np.exp(wl.gaussian_random_field(shape, 1.0, 0.1, 2))
+    op = oracle.Operator("3d7_vark", shape, k=k)
+    r = wl.normal_rhs(op.n, 4)
+    dinv = 1.0 / op.diag()
+    for s in (1, 2, 3, 5):
+        P, vm = oracle.mpk_cvm(op, r, s)
+        z = dinv * r
+        for j in range(s):
+            assert np.array_equal(P[j], z)
+            Az = op.apply(z)
+            assert np.array_equal(P[s + j], Az)
+            z = dinv * Az
+        Z = P[:s].T
+        AZ = np.stack([op.apply(Z[:, b]) for b in range(s)], axis=1)
+        G = Z.T @ AZ
+        for a in range(s):
+            for b in range(s):
+                assert G[a, b] == pytest.approx(vm[a + b + 1], rel=1e-10)
+        # moments from their definition: mu_q = r^T K^q B^-1 r
+        u = dinv * r
+        for q in range(2 * s):
+            assert vm[q] == pytest.approx(r @ u, rel=1e-10)
+            u = dinv * op.apply(u)
