@@ -108,8 +108,13 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-27pt", action="store_true",
+                    help="skip the 256^3 27-point FP64 / mixed-precision comparison")
     ap.add_argument("--only-timed", action="store_true",
                     help="only the timed solves (for profiler runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only a plain 1 GiB device-to-device copy, three times (the "
+                         "reference for the FETCH_SIZE / WRITE_SIZE counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no sharding or collectives); "
@@ -121,6 +126,14 @@ def main():
     from paper_2501_03743_amd import workloads as wl
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 8, "copies": 3}))
+        return
     H = sstep.Handle(0)
     n = N ** 3
     A = H.matrix_csr_from_stencil("3d7", (N, N, N))
@@ -215,6 +228,39 @@ def main():
         per_s[str(s)] = {"tts_s": t, "outer": r.outer, "status": r.status,
                          "true_rel": r.true_rel}
 
+    # 3D 27-point 256^3 (n = 16.8M, 449M stored entries), Jacobi, s = 4, to rtol 1e-10:
+    # plain FP64 s-step and standard CG versus the FP32-inner / FP64-refinement form;
+    # errors against an FP64 s-step solve to rtol 1e-13 (which the parity tests tie to
+    # the oracle at smaller sizes)
+    config2 = None
+    if not args.skip_27pt:
+        N2 = 256
+        A2 = H.matrix_csr_from_stencil("3d27", (N2, N2, N2))
+        b2 = torch.from_numpy(wl.normal_rhs(N2 ** 3, SEED)).cuda()
+        x2 = torch.zeros_like(b2)
+        xref = torch.zeros_like(b2)
+        rref = H.solve(A2, b2, xref, s=S, rtol=1e-13, maxit=MAXIT)
+
+        def run2(**kw):
+            x2.zero_()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            rr = H.solve(A2, b2, x2, rtol=1e-10, maxit=MAXIT, **kw)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            err = float(torch.linalg.vector_norm(x2 - xref) / torch.linalg.vector_norm(xref))
+            return {"tts_s": dt, "status": rr.status, "outer": rr.outer, "true_rel": rr.true_rel,
+                    "rel_err_vs_fp64_ref": err, "refinements": len(rr.hist) - 1}
+        run2(s=S, precision="mixed_ir")   # first use builds the FP32 copy
+        config2 = {"workload": "3D 27-point 256^3 (n=16777216, nnz=%d), CSR, Jacobi, s=4, "
+                               "b~N(0,1) seed 0, rtol 1e-10" % A2.nnz,
+                   "fp64_ref_true_rel": rref.true_rel,
+                   "sstep_fp64": run2(s=S),
+                   "sstep_mixed_ir": run2(s=S, precision="mixed_ir"),
+                   "pcg_fp64": run2(method="pcg")}
+        A2.close()
+        del b2, x2, xref
+
     out = {
         "metric": "time-to-solution @rtol 1e-8 (s) + SpMV/matrix-powers HBM GB/s, s-step vs CG",
         "value": tts,
@@ -253,6 +299,7 @@ def main():
             "sstep_csr_by_s": per_s,
             "spmv": spmv,
         },
+        "config_27pt_256_mixed": config2,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(res.outer)

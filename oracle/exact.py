@@ -67,9 +67,12 @@ def _solve(M, rhs):
     return y
 
 
-def sstep(A, b, bdiag, s, outer):
+def sstep(A, b, bdiag, s, outer, b1_printed_bound=False):
     """Alg. 3 for ``outer`` outer iterations.  Returns a dict with the iterates
-    x_i and, per iteration, vm, alpha, beta and W (exact)."""
+    x_i and, per iteration, vm, alpha, beta and W (exact).
+
+    ``b1_printed_bound`` fills b1 only for j < i, as the printed loop bound of
+    Alg. 6 reads (tests use it to show that this reading breaks the method)."""
     n = len(b)
     x = [Fr(0)] * n
     r = list(map(Fr, b))
@@ -100,7 +103,8 @@ def sstep(A, b, bdiag, s, outer):
                 for j in range(1, i):
                     t += rhs[s - 1 + j - 1] * alpha_prev[s - i + j - 1]
                 rhs[s - 1 + i - 1] = -t / alpha_prev[s - 1]
-            b1 = [[-rhs[i + j] for j in range(s)] for i in range(s)]
+            b1 = [[-rhs[i + j] if (not b1_printed_bound or j < i) else Fr(0)
+                   for j in range(s)] for i in range(s)]
             bcols = [_solve(W_prev, [b1[i][j] for i in range(s)]) for j in range(s)]
             beta = [[bcols[j][i] for j in range(s)] for i in range(s)]
             W = [[H[i][j] - sum((b1[i][q] * beta[q][j] for q in range(s)), Fr(0))

@@ -1,190 +1,35 @@
 // libsstep: the C ABI declared in include/sstep.h, on top of the gfx950
-// kernels of kernels.hpp.  Host code only orders launches on the handle's
-// stream, polls the device status word every few outer iterations and copies
-// results back; every arithmetic step of a solve runs in the kernels.
-#include "sstep.h"
-
-#include <hip/hip_runtime.h>
-
-#include <algorithm>
-#include <cmath>
-#include <cstdio>
-#include <cstring>
-#include <string>
-#include <vector>
-
-#include "kernels.hpp"
+// kernels.  Host code only orders launches on the handle's stream, polls the
+// device status word every few outer iterations and copies results back;
+// every arithmetic step of a solve runs in the kernels.
+#include "engine.hpp"
+#include "setup_kernels.hpp"
 
 using namespace ssp;
 
 namespace {
-
-struct Workspace {
-  int64_t n = 0, ld = 0;
-  int s = 0;
-  double *P1 = nullptr, *P2 = nullptr;   // n x 2s blocks, column-major, leading dim ld
-  double *r = nullptr;
-  double *pcg_p = nullptr, *pcg_s = nullptr;
-  double *partials = nullptr;            // kGridMax x 2*kSMax
-  double *hist = nullptr;
-  int hist_cap = 0;
-};
-
-}  // namespace
-
-struct ssp_handle {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  std::string err;
-  Workspace ws;
-  DevState *st = nullptr;          // device control block
-  DevState *h_init = nullptr;      // pinned staging for the control block
-  DevState *h_read = nullptr;      // pinned readback
-  // results of the last solve
-  int last_outer = 0, last_s = 1;
-  double last_true_rel = NAN;
-  std::vector<double> last_hist;
-  // profiling
-  bool prof_on = false;
-  std::vector<hipEvent_t> ev;
-  std::vector<int> ev_cls;
-  size_t ev_used = 0;
-  int prof_launch[4] = {0, 0, 0, 0};
-  double prof_ms[4] = {0, 0, 0, 0};
-};
-
-struct ssp_matrix {
-  ssp_handle *h = nullptr;
-  int kind = 0;                  // 0 = CSR, else SSP_STENCIL_*
-  int64_t n = 0, nnz = 0;
-  CsrArgs csr{};
-  int32_t *own_rowptr = nullptr, *own_colind = nullptr;
-  double *own_val = nullptr;
-  StencilArgs sten{};
-  double *dinv = nullptr;        // Jacobi vector (CSR, VARK)
-  double dconst = 1.0;           // Jacobi constant (constant-diagonal stencils)
-  int prec = SSP_PREC_JACOBI;
-};
-
-namespace {
-
-int fail(ssp_handle *h, int code, const std::string &msg) {
-  if (h) h->err = msg;
-  return code;
-}
-
-#define HIPCHK(h, call)                                                               \
-  do {                                                                                \
-    hipError_t e_ = (call);                                                           \
-    if (e_ != hipSuccess)                                                             \
-      return fail((h), SSP_EHIP, std::string("HIP error ") + hipGetErrorString(e_) +  \
-                                     " (line " + std::to_string(__LINE__) + ")");     \
-  } while (0)
-
-#define LAUNCHCHK(h) HIPCHK(h, hipGetLastError())
-
-Prec prec_of(const ssp_matrix *A) {
-  if (A->prec == SSP_PREC_NONE) return Prec{nullptr, 1.0};
-  if (A->dinv) return Prec{A->dinv, 0.0};
-  return Prec{nullptr, A->dconst};
-}
-
-int grid_rows(int64_t n) {
-  int64_t g = (n + kWG - 1) / kWG;
-  if (g > kGridMax) g = kGridMax;
-  if (g < 1) g = 1;
-  return (int)g;
-}
-
-int grid_of(const ssp_matrix *A) {
-  if (A->kind == 0 && A->csr.variant == CSR_STAGED) {
-    int64_t g = A->csr.nrb;
-    if (g > kGridMax) g = kGridMax;
-    return (int)std::max<int64_t>(g, 1);
-  }
-  return grid_rows(A->n);
-}
-
-// profiling: event pairs around launches, by class (0 matrix powers j < s and plain
-// SpMV, 1 last power with moments and s x s solve, 2 vector/block updates, 3 other)
-void prof_begin(ssp_handle *h, int cls) {
-  if (!h->prof_on) return;
-  if (h->ev_used + 2 > h->ev.size()) {
-    for (int i = 0; i < 64; ++i) {
-      hipEvent_t e;
-      if (hipEventCreate(&e) != hipSuccess) return;
-      h->ev.push_back(e);
-    }
-    h->ev_cls.resize(h->ev.size() / 2 + 64);
-  }
-  h->ev_cls[h->ev_used / 2] = cls;
-  (void)hipEventRecord(h->ev[h->ev_used], h->stream);
-}
-void prof_end(ssp_handle *h) {
-  if (!h->prof_on || h->ev_used + 2 > h->ev.size()) return;
-  (void)hipEventRecord(h->ev[h->ev_used + 1], h->stream);
-  h->ev_used += 2;
-}
-void prof_collect(ssp_handle *h) {
-  if (!h->prof_on) return;
-  for (size_t i = 0; i + 1 < h->ev_used; i += 2) {
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, h->ev[i], h->ev[i + 1]) == hipSuccess) {
-      const int c = h->ev_cls[i / 2];
-      h->prof_launch[c] += 1;
-      h->prof_ms[c] += ms;
-    }
-  }
-  h->ev_used = 0;
-}
-
-template <class Epi>
-int launch_op(ssp_handle *h, const ssp_matrix *A, const double *x, const Epi &epi, int cls) {
-  const int G = grid_of(A);
-  prof_begin(h, cls);
-  switch (A->kind) {
-    case 0:
-      k_csr<Epi><<<G, kWG, 0, h->stream>>>(A->csr, x, epi, h->st, h->ws.partials);
-      break;
-    case SSP_STENCIL_2D5:
-      k_stencil<K_2D5, Epi><<<G, kWG, 0, h->stream>>>(A->sten, x, epi, h->st, h->ws.partials);
-      break;
-    case SSP_STENCIL_3D7:
-      k_stencil<K_3D7, Epi><<<G, kWG, 0, h->stream>>>(A->sten, x, epi, h->st, h->ws.partials);
-      break;
-    case SSP_STENCIL_3D27:
-      k_stencil<K_3D27, Epi><<<G, kWG, 0, h->stream>>>(A->sten, x, epi, h->st, h->ws.partials);
-      break;
-    case SSP_STENCIL_3D7_VARK:
-      k_stencil<K_VARK, Epi><<<G, kWG, 0, h->stream>>>(A->sten, x, epi, h->st, h->ws.partials);
-      break;
-    default:
-      return fail(h, SSP_EINVAL, "unknown operator kind " + std::to_string(A->kind));
-  }
-  if constexpr (Epi::NP > 0) {
-    k_finalize<Epi><<<1, kWG, 0, h->stream>>>(epi, h->st, h->ws.partials, G);
-  }
-  prof_end(h);
-  LAUNCHCHK(h);
-  return SSP_OK;
-}
 
 void hfree(void *&p) {
   if (p) (void)hipFree(p);
   p = nullptr;
 }
 
+template <typename P>
+void hfree_t(P *&p) {
+  void *q = (void *)p;
+  hfree(q);
+  p = nullptr;
+}
+
 int ensure_workspace(ssp_handle *h, int64_t n, int s, int hist_need, bool pcg) {
   Workspace &w = h->ws;
-  if (!w.partials) {
-    HIPCHK(h, hipMalloc(&w.partials, sizeof(double) * kGridMax * 2 * kSMax));
-  }
+  if (!w.partials) HIPCHK(h, hipMalloc(&w.partials, sizeof(double) * kGridMax * 2 * kSMax));
   if (n > w.n || s > w.s) {
-    hfree((void *&)w.P1);
-    hfree((void *&)w.P2);
-    hfree((void *&)w.r);
-    hfree((void *&)w.pcg_p);
-    hfree((void *&)w.pcg_s);
+    hfree_t(w.P1);
+    hfree_t(w.P2);
+    hfree_t(w.r);
+    hfree_t(w.pcg_p);
+    hfree_t(w.pcg_s);
     const int64_t nn = std::max(n, w.n);
     const int ss = std::max(s, w.s);
     const int64_t ld = (nn + 31) / 32 * 32;  // 256-byte column alignment
@@ -192,9 +37,9 @@ int ensure_workspace(ssp_handle *h, int64_t n, int s, int hist_need, bool pcg) {
         hipMalloc(&w.P2, sizeof(double) * ld * 2 * ss) != hipSuccess ||
         hipMalloc(&w.r, sizeof(double) * ld) != hipSuccess) {
       (void)hipGetLastError();
-      hfree((void *&)w.P1);
-      hfree((void *&)w.P2);
-      hfree((void *&)w.r);
+      hfree_t(w.P1);
+      hfree_t(w.P2);
+      hfree_t(w.r);
       w.n = w.s = 0;
       return fail(h, SSP_ENOMEM, "workspace allocation failed (n=" + std::to_string(n) + ")");
     }
@@ -206,13 +51,13 @@ int ensure_workspace(ssp_handle *h, int64_t n, int s, int hist_need, bool pcg) {
     if (hipMalloc(&w.pcg_p, sizeof(double) * w.ld) != hipSuccess ||
         hipMalloc(&w.pcg_s, sizeof(double) * w.ld) != hipSuccess) {
       (void)hipGetLastError();
-      hfree((void *&)w.pcg_p);
-      hfree((void *&)w.pcg_s);
+      hfree_t(w.pcg_p);
+      hfree_t(w.pcg_s);
       return fail(h, SSP_ENOMEM, "workspace allocation failed (n=" + std::to_string(n) + ")");
     }
   }
   if (hist_need > w.hist_cap) {
-    hfree((void *&)w.hist);
+    hfree_t(w.hist);
     const int cap = std::max(hist_need, 1024);
     if (hipMalloc(&w.hist, sizeof(double) * cap) != hipSuccess) {
       (void)hipGetLastError();
@@ -224,8 +69,37 @@ int ensure_workspace(ssp_handle *h, int64_t n, int s, int hist_need, bool pcg) {
   return SSP_OK;
 }
 
-// Writes the header of the device control block (status, counters, options).
-int state_init(ssp_handle *h, int s, int outer_max, int fixed, double rtol) {
+// FP32 blocks and vectors of the inner solves of mixed-precision refinement.
+int ensure_workspace32(ssp_handle *h, int64_t n, int s) {
+  Workspace &w = h->ws;
+  if (n <= w.n32 && s <= w.s32) return SSP_OK;
+  hfree_t(w.Q1);
+  hfree_t(w.Q2);
+  hfree_t(w.r32);
+  hfree_t(w.d32);
+  const int64_t nn = std::max(n, w.n32);
+  const int ss = std::max(s, w.s32);
+  const int64_t ld = (nn + 63) / 64 * 64;
+  if (hipMalloc(&w.Q1, sizeof(float) * ld * 2 * ss) != hipSuccess ||
+      hipMalloc(&w.Q2, sizeof(float) * ld * 2 * ss) != hipSuccess ||
+      hipMalloc(&w.r32, sizeof(float) * ld) != hipSuccess ||
+      hipMalloc(&w.d32, sizeof(float) * ld) != hipSuccess) {
+    (void)hipGetLastError();
+    hfree_t(w.Q1);
+    hfree_t(w.Q2);
+    hfree_t(w.r32);
+    hfree_t(w.d32);
+    w.n32 = w.s32 = 0;
+    return fail(h, SSP_ENOMEM, "FP32 workspace allocation failed (n=" + std::to_string(n) + ")");
+  }
+  w.n32 = nn;
+  w.s32 = ss;
+  w.ld32 = ld;
+  return SSP_OK;
+}
+
+// Writes the header of the device control block (status, options).
+int state_init(ssp_handle *h, int s, int outer_max, int fixed, double rtol, int hist_cap) {
   DevState *c = h->h_init;
   HIPCHK(h, hipStreamSynchronize(h->stream));  // staging buffer reuse
   memset(c, 0, offsetof(DevState, vm));
@@ -234,7 +108,7 @@ int state_init(ssp_handle *h, int s, int outer_max, int fixed, double rtol) {
   c->outer_max = outer_max;
   c->fixed = fixed;
   c->s = s;
-  c->hist_cap = h->ws.hist_cap;
+  c->hist_cap = hist_cap;
   c->rtol = rtol;
   HIPCHK(h, hipMemcpyAsync(h->st, c, offsetof(DevState, vm), hipMemcpyHostToDevice, h->stream));
   return SSP_OK;
@@ -247,100 +121,13 @@ int read_state(ssp_handle *h, bool whole) {
   return SSP_OK;
 }
 
-// One outer iteration of the s-step method: s matrix-power launches (the last
-// one fused with the moments and the s x s solve) and the fused update.
-template <int S>
-int sstep_iteration(ssp_handle *h, const ssp_matrix *A, double *x, int k) {
-  Workspace &w = h->ws;
-  double *Pc = (k % 2 == 0) ? w.P2 : w.P1;   // Alg. 3: even k fills P2, odd k fills P1
-  double *Po = (k % 2 == 0) ? w.P1 : w.P2;
-  const Prec pc = prec_of(A);
-  for (int j = 1; j <= S; ++j) {
-    const double *zin = Pc + (int64_t)(j - 1) * w.ld;
-    double *az = Pc + (int64_t)(S + j - 1) * w.ld;
-    int rc;
-    if (j < S) {
-      rc = launch_op(h, A, zin, EpiMpk{az, Pc + (int64_t)j * w.ld, pc}, 0);
-    } else {
-      rc = launch_op(h, A, zin, EpiMpkLast<S>{az, Pc, w.ld, w.r, 1}, 1);
-    }
-    if (rc) return rc;
-  }
-  const int G = grid_rows(A->n);
-  prof_begin(h, 2);
-  k_update<S><<<G, kWG, 0, h->stream>>>(A->n, w.ld, Pc, Po, x, w.r, pc, h->st, w.partials);
-  k_finalize<FinUpdate><<<1, kWG, 0, h->stream>>>(FinUpdate{w.hist}, h->st, w.partials, G);
-  prof_end(h);
-  LAUNCHCHK(h);
-  return SSP_OK;
-}
-
-typedef int (*iter_fn)(ssp_handle *, const ssp_matrix *, double *, int);
-
-template <int S>
-int mpk_only(ssp_handle *h, const ssp_matrix *A, const double *r, double *P, int64_t ld) {
-  const Prec pc = prec_of(A);
-  const int G = grid_rows(A->n);
-  k_prec<<<G, kWG, 0, h->stream>>>(A->n, r, P, pc);
-  LAUNCHCHK(h);
-  for (int j = 1; j <= S; ++j) {
-    const double *zin = P + (int64_t)(j - 1) * ld;
-    double *az = P + (int64_t)(S + j - 1) * ld;
-    int rc;
-    if (j < S) rc = launch_op(h, A, zin, EpiMpk{az, P + (int64_t)j * ld, pc}, 0);
-    else rc = launch_op(h, A, zin, EpiMpkLast<S>{az, P, ld, r, 0}, 1);
-    if (rc) return rc;
-  }
-  return SSP_OK;
-}
-
-typedef int (*mpk_fn)(ssp_handle *, const ssp_matrix *, const double *, double *, int64_t);
-
-template <int... Ss>
-struct Dispatch {
-  static iter_fn iter(int s) {
-    iter_fn f = nullptr;
-    ((s == Ss ? (f = &sstep_iteration<Ss>, 0) : 0), ...);
-    return f;
-  }
-  static mpk_fn mpk(int s) {
-    mpk_fn f = nullptr;
-    ((s == Ss ? (f = &mpk_only<Ss>, 0) : 0), ...);
-    return f;
-  }
-};
-using SDispatch = Dispatch<1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16>;
-
 int check_matrix(ssp_handle *h, const ssp_matrix *A) {
   if (!A || A->h != h) return fail(h, SSP_EINVAL, "matrix is NULL or belongs to another handle");
   return SSP_OK;
 }
 
-int finish_solve(ssp_handle *h, const ssp_matrix *A, const double *b, double *x, int s,
-                 int outer_max) {
-  // status and the true residual of the returned iterate
-  int rc = read_state(h, false);
-  if (rc) return rc;
-  const int status = h->h_read->status;
-  if (status == ST_ZERO_RHS) HIPCHK(h, hipMemsetAsync(x, 0, sizeof(double) * A->n, h->stream));
-  rc = launch_op(h, A, x, EpiTrueRes{b}, 3);
-  if (rc) return rc;
-  rc = read_state(h, true);
-  if (rc) return rc;
-  prof_collect(h);
-  const DevState &d = *h->h_read;
-  h->last_s = s;
-  h->last_outer = (status == ST_ZERO_RHS) ? 0 : d.k;
-  const double bn = std::sqrt(d.bb);
-  h->last_true_rel = (status == ST_ZERO_RHS || bn == 0.0) ? 0.0 : std::sqrt(d.true_rr) / bn;
-  const int len = std::min(h->last_outer + 1, h->ws.hist_cap);
-  h->last_hist.assign(len, 0.0);
-  if (status != ST_ZERO_RHS && len > 0) {
-    HIPCHK(h, hipMemcpy(h->last_hist.data(), h->ws.hist, sizeof(double) * len,
-                        hipMemcpyDeviceToHost));
-  }
-  (void)outer_max;
-  switch (status) {
+int status_code(int st) {
+  switch (st) {
     case ST_CONVERGED:
     case ST_ZERO_RHS:
       return SSP_OK;
@@ -349,6 +136,356 @@ int finish_solve(ssp_handle *h, const ssp_matrix *A, const double *b, double *x,
     default:
       return SSP_NOT_CONVERGED;
   }
+}
+
+// The true residual of the returned iterate and the results of the solve.
+int finish_solve(ssp_handle *h, const ssp_matrix *A, const double *b, double *x, int s) {
+  int rc = read_state(h, false);
+  if (rc) return rc;
+  const int status = h->h_read->status;
+  if (status == ST_ZERO_RHS) HIPCHK(h, hipMemsetAsync(x, 0, sizeof(double) * A->n, h->stream));
+  rc = launch_op<double>(h, A, x, EpiTrueRes{b}, 3);
+  if (rc) return rc;
+  rc = read_state(h, true);
+  if (rc) return rc;
+  const DevState &d = *h->h_read;
+  // the iteration that broke down ran its matrix powers as well
+  prof_collect(h, d.k + (status == ST_BREAKDOWN ? 1 : 0));
+  h->prof_iter = -1;
+  h->last_s = s;
+  h->last_outer = (status == ST_ZERO_RHS) ? 0 : d.k;
+  const double bn = std::sqrt(d.bb);
+  h->last_true_rel = (status == ST_ZERO_RHS || bn == 0.0) ? 0.0 : std::sqrt(d.true_rr) / bn;
+  const int len = std::min(h->last_outer + 1, h->ws.hist_cap);
+  h->last_hist.assign(len, 0.0);
+  if (status != ST_ZERO_RHS && len > 0)
+    HIPCHK(h, hipMemcpy(h->last_hist.data(), h->ws.hist, sizeof(double) * len,
+                        hipMemcpyDeviceToHost));
+  return status_code(status);
+}
+
+// Builds the FP32 copy of a matrix (values, coefficients, Jacobi vector).
+int ensure_fp32(ssp_handle *h, ssp_matrix *A) {
+  if (A->has32) return SSP_OK;
+  const unsigned nb = (unsigned)((A->n + kWG - 1) / kWG);
+  if (A->kind == 0) {
+    if (hipMalloc(&A->val32, sizeof(float) * A->nnz) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(h, SSP_ENOMEM, "FP32 matrix allocation failed");
+    }
+    const unsigned nbz = (unsigned)((A->nnz + kWG - 1) / kWG);
+    k_to_float<<<nbz, kWG, 0, h->stream>>>(A->nnz, A->csr.val, A->val32);
+    LAUNCHCHK(h);
+    A->csr32 = CsrArgs<float>{A->csr.n, A->csr.rowptr, A->csr.colind, A->val32,
+                              A->csr.rows_per_rb, A->csr.nrb, A->csr.variant};
+  } else {
+    const StencilArgs<double> &S = A->sten;
+    A->sten32 = StencilArgs<float>{S.n, S.nx, S.ny, S.nz, S.fx, S.fy, (float)S.diag,
+                                   (float)S.off, nullptr};
+    if (A->kind == SSP_STENCIL_3D7_VARK) {
+      if (hipMalloc(&A->k32, sizeof(float) * A->n) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(h, SSP_ENOMEM, "FP32 coefficient allocation failed");
+      }
+      k_to_float<<<nb, kWG, 0, h->stream>>>(A->n, S.k, A->k32);
+      LAUNCHCHK(h);
+      A->sten32.k = A->k32;
+    }
+  }
+  if (A->dinv) {
+    if (hipMalloc(&A->dinv32, sizeof(float) * A->n) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(h, SSP_ENOMEM, "FP32 Jacobi allocation failed");
+    }
+    k_to_float<<<nb, kWG, 0, h->stream>>>(A->n, A->dinv, A->dinv32);
+    LAUNCHCHK(h);
+  }
+  A->has32 = true;
+  return SSP_OK;
+}
+
+// Both CSR kernels give bitwise-identical products; pick the faster one for
+// this matrix by timing a few products (SSP_CSR_VARIANT=0/1 forces one).
+int csr_pick_variant(ssp_handle *h, ssp_matrix *A) {
+  const char *env = getenv("SSP_CSR_VARIANT");
+  if (env && (env[0] == '0' || env[0] == '1')) {
+    A->csr.variant = env[0] - '0';
+    return SSP_OK;
+  }
+  A->csr.variant = CSR_STAGED;
+  h->prof_on = false;
+  int rc = ensure_workspace(h, 1, 1, 1, false);
+  if (rc) return rc;
+  double *y = nullptr;
+  HIPCHK(h, hipMalloc(&y, sizeof(double) * A->n));
+  hipEvent_t e0, e1;
+  HIPCHK(h, hipEventCreate(&e0));
+  HIPCHK(h, hipEventCreate(&e1));
+  float best = 1e30f;
+  int best_v = CSR_STAGED;
+  for (int v = CSR_STAGED; v <= CSR_ROW && rc == SSP_OK; ++v) {
+    A->csr.variant = v;
+    rc = launch_op<double>(h, A, A->dinv, EpiStore<double>{y}, 0);  // warm-up
+    if (rc) break;
+    (void)hipEventRecord(e0, h->stream);
+    for (int t = 0; t < 3 && rc == SSP_OK; ++t)
+      rc = launch_op<double>(h, A, A->dinv, EpiStore<double>{y}, 0);
+    (void)hipEventRecord(e1, h->stream);
+    (void)hipEventSynchronize(e1);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms < best) {
+      best = ms;
+      best_v = v;
+    }
+  }
+  A->csr.variant = best_v;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(y);
+  return rc;
+}
+
+int csr_finish_setup(ssp_handle *h, ssp_matrix *A) {
+  // longest row -> rows per LDS block; Jacobi vector; kernel form
+  int *d_max = nullptr;
+  HIPCHK(h, hipMalloc(&d_max, sizeof(int)));
+  HIPCHK(h, hipMemsetAsync(d_max, 0, sizeof(int), h->stream));
+  const int64_t nb = (A->n + kWG - 1) / kWG;
+  k_csr_maxrow<<<(unsigned)nb, kWG, 0, h->stream>>>(A->n, A->csr.rowptr, d_max);
+  LAUNCHCHK(h);
+  int maxrow = 0;
+  HIPCHK(h, hipMemcpyAsync(&maxrow, d_max, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  (void)hipFree(d_max);
+  int R = maxrow > 0 ? kCsrLds / maxrow : kCsrRowsMax;
+  if (R > kCsrRowsMax) R = kCsrRowsMax;
+  if (R < 1) R = 1;
+  A->csr.rows_per_rb = R;
+  A->csr.nrb = (A->n + R - 1) / R;
+  HIPCHK(h, hipMalloc(&A->dinv, sizeof(double) * A->n));
+  k_csr_dinv<<<(unsigned)nb, kWG, 0, h->stream>>>(A->n, A->csr.rowptr, A->csr.colind,
+                                                  A->csr.val, A->dinv);
+  LAUNCHCHK(h);
+  return csr_pick_variant(h, A);
+}
+
+int stencil_args(ssp_handle *h, int kind, int nx, int ny, int nz, const double *coef,
+                 ssp_matrix *A) {
+  if (nx < 1 || ny < 1 || nz < 1 || (kind == SSP_STENCIL_2D5 && nz != 1) ||
+      kind < SSP_STENCIL_2D5 || kind > SSP_STENCIL_3D7_VARK)
+    return fail(h, SSP_EINVAL, "invalid stencil kind or grid (kind=" + std::to_string(kind) + ")");
+  const int64_t n = (int64_t)nx * ny * nz;
+  if (n >= (int64_t)1 << 31) return fail(h, SSP_EINVAL, "grid too large (n=" + std::to_string(n) + ")");
+  StencilArgs<double> &S = A->sten;
+  S.n = n;
+  S.nx = nx;
+  S.ny = ny;
+  S.nz = nz;
+  S.fx = FastDiv{nx, 1.0 / nx};
+  S.fy = FastDiv{ny, 1.0 / ny};
+  S.k = nullptr;
+  A->n = n;
+  if (kind == SSP_STENCIL_3D7_VARK) {
+    if (!coef) return fail(h, SSP_EINVAL, "3D7_VARK needs the device coefficient array");
+    S.k = coef;
+    S.diag = S.off = 0.0;
+  } else {
+    const double dflt[4][2] = {{0, 0}, {4.0, -1.0}, {6.0, -1.0}, {26.0, -1.0}};
+    S.diag = coef ? coef[0] : dflt[kind][0];
+    S.off = coef ? coef[1] : dflt[kind][1];
+  }
+  A->nnz = (kind == SSP_STENCIL_3D27) ? (int64_t)(3 * nx - 2) * (3 * ny - 2) * (3 * nz - 2)
+           : (kind == SSP_STENCIL_2D5)
+               ? 5LL * nx * ny - 2LL * nx - 2LL * ny
+               : 7LL * nx * ny * nz - 2LL * nx * ny - 2LL * ny * nz - 2LL * nx * nz;
+  return SSP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// solves
+// ---------------------------------------------------------------------------
+
+int solve_sstep(ssp_handle *h, const ssp_matrix *A, const double *b, double *x, int s,
+                double rtol, int maxit, const ssp_opts *o) {
+  const int fixed = (o && o->fixed_outer > 0) ? o->fixed_outer : 0;
+  const int outer_max = fixed ? fixed : (int)((maxit + (int64_t)s - 1) / s);
+  int rc = ensure_workspace(h, A->n, s, outer_max + 1, false);
+  if (rc) return rc;
+  Workspace &w = h->ws;
+  rc = state_init(h, s, outer_max, fixed ? 1 : 0, rtol, w.hist_cap);
+  if (rc) return rc;
+  double *tag = nullptr;
+  // r = b - A x0 and z1 = B^-1 r into column 1 of the block used at k = 0
+  rc = launch_op<double>(h, A, x, EpiInit{b, w.r, w.P2, prec_of(A, tag), w.hist}, 3);
+  if (rc) return rc;
+  const iter_fn<double> step = iteration_f64(s);
+  const IterBufs<double> B{w.P1, w.P2, w.ld, x, w.r};
+  const int trace_cap = (o && o->trace_cap > 0 && o->trace_vm && o->trace_alpha &&
+                         o->trace_beta && o->trace_W) ? o->trace_cap : 0;
+  int every = (o && o->check_every > 0) ? o->check_every : std::max(1, 32 / s);
+  if (trace_cap) every = 1;
+  int k = 0;
+  rc = read_state(h, false);
+  if (rc) return rc;
+  while (k < outer_max && h->h_read->status == ST_RUNNING) {
+    const int m = std::min(every, outer_max - k);
+    for (int i = 0; i < m; ++i, ++k) {
+      h->prof_iter = k;
+      rc = step(h, A, B, k);
+      if (rc) return rc;
+    }
+    h->prof_iter = -1;
+    rc = read_state(h, trace_cap > 0);
+    if (rc) return rc;
+    if (trace_cap) {
+      const DevState &d = *h->h_read;
+      const int it = d.k - 1;  // iteration whose coefficients are in the block
+      if (d.k == k && it < trace_cap) {
+        memcpy(o->trace_vm + (size_t)it * 2 * s, d.vm, sizeof(double) * 2 * s);
+        memcpy(o->trace_alpha + (size_t)it * s, d.alpha, sizeof(double) * s);
+        memcpy(o->trace_beta + (size_t)it * s * s, d.beta, sizeof(double) * s * s);
+        memcpy(o->trace_W + (size_t)it * s * s, d.W, sizeof(double) * s * s);
+      }
+    }
+  }
+  return finish_solve(h, A, b, x, s);
+}
+
+int solve_pcg(ssp_handle *h, const ssp_matrix *A, const double *b, double *x, double rtol,
+              int maxit, const ssp_opts *o) {
+  const int fixed = (o && o->fixed_outer > 0) ? o->fixed_outer : 0;
+  const int outer_max = fixed ? fixed : maxit;
+  int rc = ensure_workspace(h, A->n, 1, outer_max + 1, true);
+  if (rc) return rc;
+  Workspace &w = h->ws;
+  rc = state_init(h, 1, outer_max, fixed ? 1 : 0, rtol, w.hist_cap);
+  if (rc) return rc;
+  double *tag = nullptr;
+  const Prec<double> pc = prec_of(A, tag);
+  rc = launch_op<double>(h, A, x, EpiPcgInit{b, w.r, w.pcg_p, pc, w.hist}, 3);
+  if (rc) return rc;
+  const int every = (o && o->check_every > 0) ? o->check_every : 32;
+  const int G = grid_rows(A->n);
+  int k = 0;
+  rc = read_state(h, false);
+  if (rc) return rc;
+  while (k < outer_max && h->h_read->status == ST_RUNNING) {
+    const int m = std::min(every, outer_max - k);
+    for (int i = 0; i < m; ++i, ++k) {
+      h->prof_iter = k;
+      rc = launch_op<double>(h, A, w.pcg_p, EpiPcgSpmv{w.pcg_p, w.pcg_s}, 0);
+      if (rc) return rc;
+      prof_begin(h, 2);
+      k_pcg_update<<<G, kWG, 0, h->stream>>>(A->n, x, w.r, w.pcg_p, w.pcg_s, pc, h->st,
+                                             w.partials);
+      k_finalize<FinPcgUpdate><<<1, kWG, 0, h->stream>>>(FinPcgUpdate{w.hist}, h->st, w.partials,
+                                                         G);
+      prof_end(h);
+      LAUNCHCHK(h);
+      prof_begin(h, 2);
+      k_pcg_direction<<<G, kWG, 0, h->stream>>>(A->n, w.r, w.pcg_p, pc, h->st);
+      prof_end(h);
+      LAUNCHCHK(h);
+    }
+    h->prof_iter = -1;
+    rc = read_state(h, false);
+    if (rc) return rc;
+  }
+  return finish_solve(h, A, b, x, 1);
+}
+
+// Mixed precision: FP32 inner s-step solves (matrix powers and block updates
+// in FP32; moments, s x s solves and the inner stopping test in FP64) of
+// A d = r inside FP64 iterative refinement x += d, r = b - A x.
+int solve_mixed(ssp_handle *h, ssp_matrix *A, const double *b, double *x, int s, double rtol,
+                int maxit, const ssp_opts *o) {
+  if (s > kSMaxF32)
+    return fail(h, SSP_EUNSUPPORTED, "mixed precision supports s <= " + std::to_string(kSMaxF32));
+  const double inner_rtol = (o && o->inner_rtol > 0.0) ? o->inner_rtol : 1e-5;
+  const int max_refine = (o && o->max_refine > 0) ? o->max_refine : 10;
+  const int inner_max = (int)((maxit + (int64_t)s - 1) / s);
+  int rc = ensure_workspace(h, A->n, 1, std::max(max_refine + 1, inner_max + 1), false);
+  if (rc) return rc;
+  rc = ensure_workspace32(h, A->n, s);
+  if (rc) return rc;
+  rc = ensure_fp32(h, A);
+  if (rc) return rc;
+  Workspace &w = h->ws;
+  // control block: inner-solve options plus the refinement loop's
+  rc = state_init(h, s, inner_max, 0, inner_rtol, 0);
+  if (rc) return rc;
+  {
+    DevState *c = h->h_init;
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    c->ir_refine = 0;
+    c->ir_max_refine = max_refine;
+    c->ir_hist_cap = w.hist_cap;
+    c->ir_rtol = rtol;
+    HIPCHK(h, hipMemcpyAsync(h->st, c, offsetof(DevState, vm), hipMemcpyHostToDevice, h->stream));
+  }
+  float *tag32 = nullptr;
+  const Prec<float> pc32 = prec_of(A, tag32);
+  const iter_fn<float> step = iteration_f32(s);
+  const IterBufs<float> B{w.Q1, w.Q2, w.ld32, w.d32, w.r32};
+  const int every = (o && o->check_every > 0) ? o->check_every : std::max(1, 32 / s);
+  int total_outer = 0, refine = 0, final_status = ST_MAXIT;
+  for (refine = 0; refine <= max_refine; ++refine) {
+    if (refine > 0) {
+      // x += d, then the next outer step
+      const int G = grid_rows(A->n);
+      k_ir_add<<<G, kWG, 0, h->stream>>>(A->n, x, w.d32);
+      LAUNCHCHK(h);
+      h->h_init->ir_refine = refine;  // only this field changes
+      HIPCHK(h, hipMemcpyAsync(&h->st->ir_refine, &h->h_init->ir_refine, sizeof(int),
+                               hipMemcpyHostToDevice, h->stream));
+      // the inner-solve fields the previous inner solve changed
+      HIPCHK(h, hipMemcpyAsync(&h->st->outer_max, &h->h_init->outer_max, sizeof(int),
+                               hipMemcpyHostToDevice, h->stream));
+    }
+    rc = launch_op<double>(h, A, x, EpiIrResidual{b, w.r32, w.Q2, w.d32, pc32, w.hist}, 3);
+    if (rc) return rc;
+    rc = read_state(h, false);
+    if (rc) return rc;
+    const int st = h->h_read->status;
+    if (st != ST_RUNNING) {
+      final_status = st;
+      break;
+    }
+    int k = 0;
+    while (k < inner_max && h->h_read->status == ST_RUNNING) {
+      const int m = std::min(every, inner_max - k);
+      for (int i = 0; i < m; ++i, ++k) {
+        rc = step(h, A, B, k);
+        if (rc) return rc;
+      }
+      rc = read_state(h, false);
+      if (rc) return rc;
+    }
+    const int inner_k = h->h_read->k;
+    total_outer += inner_k;
+    if (h->h_read->status == ST_BREAKDOWN && inner_k == 0) {
+      final_status = ST_BREAKDOWN;   // no progress possible
+      break;
+    }
+  }
+  h->prof_on = false;
+  // final FP64 true residual, history of the outer (true) residuals
+  if (final_status == ST_ZERO_RHS) HIPCHK(h, hipMemsetAsync(x, 0, sizeof(double) * A->n, h->stream));
+  rc = launch_op<double>(h, A, x, EpiTrueRes{b}, 3);
+  if (rc) return rc;
+  rc = read_state(h, true);
+  if (rc) return rc;
+  const DevState &d = *h->h_read;
+  h->last_s = s;
+  h->last_outer = total_outer;
+  const double bn = std::sqrt(d.ir_bb);
+  h->last_true_rel = (final_status == ST_ZERO_RHS || bn == 0.0) ? 0.0 : std::sqrt(d.true_rr) / bn;
+  const int len = std::min(std::min(refine, max_refine) + 1, w.hist_cap);
+  h->last_hist.assign(len, 0.0);
+  if (final_status != ST_ZERO_RHS && len > 0)
+    HIPCHK(h, hipMemcpy(h->last_hist.data(), w.hist, sizeof(double) * len, hipMemcpyDeviceToHost));
+  return status_code(final_status);
 }
 
 }  // namespace
@@ -389,14 +526,18 @@ int ssp_destroy(ssp_handle *h) {
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   else (void)hipDeviceSynchronize();
   Workspace &w = h->ws;
-  hfree((void *&)w.P1);
-  hfree((void *&)w.P2);
-  hfree((void *&)w.r);
-  hfree((void *&)w.pcg_p);
-  hfree((void *&)w.pcg_s);
-  hfree((void *&)w.partials);
-  hfree((void *&)w.hist);
-  hfree((void *&)h->st);
+  hfree_t(w.P1);
+  hfree_t(w.P2);
+  hfree_t(w.r);
+  hfree_t(w.pcg_p);
+  hfree_t(w.pcg_s);
+  hfree_t(w.Q1);
+  hfree_t(w.Q2);
+  hfree_t(w.r32);
+  hfree_t(w.d32);
+  hfree_t(w.partials);
+  hfree_t(w.hist);
+  hfree_t(h->st);
   if (h->h_init) (void)hipHostFree(h->h_init);
   if (h->h_read) (void)hipHostFree(h->h_read);
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
@@ -420,72 +561,6 @@ const char *ssp_status_string(int status) {
     case SSP_EUNSUPPORTED: return "unsupported combination";
     default: return "unknown status";
   }
-}
-
-// Both CSR kernels give bitwise-identical products; pick the faster one for
-// this matrix by timing a few products (SSP_CSR_VARIANT=0/1 forces one).
-static int csr_pick_variant(ssp_handle *h, ssp_matrix *A) {
-  const char *env = getenv("SSP_CSR_VARIANT");
-  if (env && (env[0] == '0' || env[0] == '1')) {
-    A->csr.variant = env[0] - '0';
-    return SSP_OK;
-  }
-  A->csr.variant = CSR_STAGED;
-  h->prof_on = false;
-  int rc = ensure_workspace(h, 1, 1, 1, false);
-  if (rc) return rc;
-  double *y = nullptr;
-  HIPCHK(h, hipMalloc(&y, sizeof(double) * A->n));
-  hipEvent_t e0, e1;
-  HIPCHK(h, hipEventCreate(&e0));
-  HIPCHK(h, hipEventCreate(&e1));
-  float best = 1e30f;
-  int best_v = CSR_STAGED;
-  for (int v = CSR_STAGED; v <= CSR_ROW; ++v) {
-    A->csr.variant = v;
-    rc = launch_op(h, A, A->dinv, EpiStore{y}, 0);  // warm-up
-    if (rc) break;
-    (void)hipEventRecord(e0, h->stream);
-    for (int t = 0; t < 3; ++t) launch_op(h, A, A->dinv, EpiStore{y}, 0);
-    (void)hipEventRecord(e1, h->stream);
-    (void)hipEventSynchronize(e1);
-    float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    if (ms < best) {
-      best = ms;
-      best_v = v;
-    }
-  }
-  A->csr.variant = best_v;
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  (void)hipFree(y);
-  return rc;
-}
-
-static int csr_finish_setup(ssp_handle *h, ssp_matrix *A) {
-  // longest row -> rows per LDS block; Jacobi vector
-  int *d_max = nullptr;
-  HIPCHK(h, hipMalloc(&d_max, sizeof(int)));
-  HIPCHK(h, hipMemsetAsync(d_max, 0, sizeof(int), h->stream));
-  const int64_t nb = (A->n + kWG - 1) / kWG;
-  k_csr_maxrow<<<(unsigned)nb, kWG, 0, h->stream>>>(A->n, A->csr.rowptr, d_max);
-  LAUNCHCHK(h);
-  int maxrow = 0;
-  HIPCHK(h, hipMemcpyAsync(&maxrow, d_max, sizeof(int), hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(h, hipStreamSynchronize(h->stream));
-  (void)hipFree(d_max);
-  // as many rows per LDS block as fit (the longest row decides)
-  int R = maxrow > 0 ? kCsrLds / maxrow : kCsrRowsMax;
-  if (R > kCsrRowsMax) R = kCsrRowsMax;
-  if (R < 1) R = 1;
-  A->csr.rows_per_rb = R;
-  A->csr.nrb = (A->n + R - 1) / R;
-  HIPCHK(h, hipMalloc(&A->dinv, sizeof(double) * A->n));
-  k_csr_dinv<<<(unsigned)nb, kWG, 0, h->stream>>>(A->n, A->csr.rowptr, A->csr.colind,
-                                                  A->csr.val, A->dinv);
-  LAUNCHCHK(h);
-  return csr_pick_variant(h, A);
 }
 
 int ssp_matrix_csr(ssp_handle *h, int64_t n, int64_t nnz, const int32_t *rowptr,
@@ -550,39 +625,6 @@ int ssp_matrix_csr(ssp_handle *h, int64_t n, int64_t nnz, const int32_t *rowptr,
   return SSP_OK;
 }
 
-static int stencil_args(ssp_handle *h, int kind, int nx, int ny, int nz, const double *coef,
-                        ssp_matrix *A) {
-  if (nx < 1 || ny < 1 || nz < 1 || (kind == SSP_STENCIL_2D5 && nz != 1) ||
-      kind < SSP_STENCIL_2D5 || kind > SSP_STENCIL_3D7_VARK)
-    return fail(h, SSP_EINVAL, "invalid stencil kind or grid (kind=" + std::to_string(kind) + ")");
-  const int64_t n = (int64_t)nx * ny * nz;
-  if (n >= (int64_t)1 << 31) return fail(h, SSP_EINVAL, "grid too large (n=" + std::to_string(n) + ")");
-  StencilArgs &S = A->sten;
-  S.n = n;
-  S.nx = nx;
-  S.ny = ny;
-  S.nz = nz;
-  S.fx = FastDiv{nx, 1.0 / nx};
-  S.fy = FastDiv{ny, 1.0 / ny};
-  S.k = nullptr;
-  A->n = n;
-  if (kind == SSP_STENCIL_3D7_VARK) {
-    if (!coef) return fail(h, SSP_EINVAL, "3D7_VARK needs the device coefficient array");
-    S.k = coef;
-    S.diag = S.off = 0.0;
-  } else {
-    const double dflt[4][2] = {{0, 0}, {4.0, -1.0}, {6.0, -1.0}, {26.0, -1.0}};
-    S.diag = coef ? coef[0] : dflt[kind][0];
-    S.off = coef ? coef[1] : dflt[kind][1];
-  }
-  const int64_t m = (kind == SSP_STENCIL_3D27) ? (int64_t)(3 * nx - 2) * (3 * ny - 2) * (3 * nz - 2)
-                    : (kind == SSP_STENCIL_2D5)
-                        ? 5LL * nx * ny - 2LL * nx - 2LL * ny
-                        : 7LL * nx * ny * nz - 2LL * nx * ny - 2LL * ny * nz - 2LL * nx * nz;
-  A->nnz = m;
-  return SSP_OK;
-}
-
 int ssp_matrix_stencil(ssp_handle *h, int kind, int nx, int ny, int nz, const double *coef,
                        ssp_matrix **out) {
   if (!h || !out) return SSP_EINVAL;
@@ -621,7 +663,7 @@ int ssp_matrix_csr_from_stencil(ssp_handle *h, int kind, int nx, int ny, int nz,
   int rc = stencil_args(h, kind, nx, ny, nz, coef, &tmp);
   if (rc) return rc;
   const int64_t n = tmp.n;
-  // row pointer on the host from the row lengths of the grid (setup only)
+  // row pointer on the host from the row lengths of the grid (set-up only)
   std::vector<int32_t> rp(n + 1);
   rp[0] = 0;
   int64_t e = 0, p = 0;
@@ -701,10 +743,13 @@ int ssp_matrix_destroy(ssp_matrix *A) {
     (void)hipSetDevice(A->h->device);
     (void)hipStreamSynchronize(A->h->stream);
   }
-  hfree((void *&)A->own_rowptr);
-  hfree((void *&)A->own_colind);
-  hfree((void *&)A->own_val);
-  hfree((void *&)A->dinv);
+  hfree_t(A->own_rowptr);
+  hfree_t(A->own_colind);
+  hfree_t(A->own_val);
+  hfree_t(A->val32);
+  hfree_t(A->k32);
+  hfree_t(A->dinv);
+  hfree_t(A->dinv32);
   delete A;
   return SSP_OK;
 }
@@ -723,7 +768,7 @@ int ssp_spmv(ssp_handle *h, const ssp_matrix *A, const double *x, double *y) {
   HIPCHK(h, hipSetDevice(h->device));
   rc = ensure_workspace(h, 1, 1, 1, false);
   if (rc) return rc;
-  return launch_op(h, A, x, EpiStore{y}, 0);
+  return launch_op<double>(h, A, x, EpiStore<double>{y}, 0);
 }
 
 int ssp_mpk(ssp_handle *h, const ssp_matrix *A, const double *r, int s, double *P, int64_t ld,
@@ -736,9 +781,9 @@ int ssp_mpk(ssp_handle *h, const ssp_matrix *A, const double *r, int s, double *
   HIPCHK(h, hipSetDevice(h->device));
   rc = ensure_workspace(h, 1, 1, 1, false);
   if (rc) return rc;
-  rc = state_init(h, s, 1, 1, 0.0);
+  rc = state_init(h, s, 1, 1, 0.0, 0);
   if (rc) return rc;
-  rc = SDispatch::mpk(s)(h, A, r, P, ld);
+  rc = mpk_f64(s)(h, A, r, P, ld);
   if (rc) return rc;
   if (vm) {
     rc = read_state(h, true);
@@ -748,102 +793,23 @@ int ssp_mpk(ssp_handle *h, const ssp_matrix *A, const double *r, int s, double *
   return SSP_OK;
 }
 
-static int solve_sstep(ssp_handle *h, const ssp_matrix *A, const double *b, double *x, int s,
-                       double rtol, int maxit, const ssp_opts *o) {
-  const int fixed = (o && o->fixed_outer > 0) ? o->fixed_outer : 0;
-  const int outer_max = fixed ? fixed : (int)((maxit + (int64_t)s - 1) / s);
-  int rc = ensure_workspace(h, A->n, s, outer_max + 1, false);
-  if (rc) return rc;
-  Workspace &w = h->ws;
-  rc = state_init(h, s, outer_max, fixed ? 1 : 0, rtol);
-  if (rc) return rc;
-  // r = b - A x0 and z1 = B^-1 r into column 1 of the block used at k = 0
-  rc = launch_op(h, A, x, EpiInit{b, w.r, w.P2, prec_of(A), w.hist}, 3);
-  if (rc) return rc;
-  const iter_fn step = SDispatch::iter(s);
-  const int trace_cap = (o && o->trace_cap > 0 && o->trace_vm && o->trace_alpha &&
-                         o->trace_beta && o->trace_W) ? o->trace_cap : 0;
-  int every = (o && o->check_every > 0) ? o->check_every : std::max(1, 32 / s);
-  if (trace_cap) every = 1;
-  int k = 0;
-  rc = read_state(h, false);
-  if (rc) return rc;
-  while (k < outer_max && h->h_read->status == ST_RUNNING) {
-    const int m = std::min(every, outer_max - k);
-    for (int i = 0; i < m; ++i, ++k) {
-      rc = step(h, A, x, k);
-      if (rc) return rc;
-    }
-    rc = read_state(h, trace_cap > 0);
-    if (rc) return rc;
-    if (trace_cap) {
-      const DevState &d = *h->h_read;
-      const int it = d.k - 1;  // iteration whose coefficients are in the block
-      if (d.k == k && it < trace_cap) {
-        memcpy(o->trace_vm + (size_t)it * 2 * s, d.vm, sizeof(double) * 2 * s);
-        memcpy(o->trace_alpha + (size_t)it * s, d.alpha, sizeof(double) * s);
-        memcpy(o->trace_beta + (size_t)it * s * s, d.beta, sizeof(double) * s * s);
-        memcpy(o->trace_W + (size_t)it * s * s, d.W, sizeof(double) * s * s);
-      }
-    }
-  }
-  return finish_solve(h, A, b, x, s, outer_max);
-}
-
-static int solve_pcg(ssp_handle *h, const ssp_matrix *A, const double *b, double *x,
-                     double rtol, int maxit, const ssp_opts *o) {
-  const int fixed = (o && o->fixed_outer > 0) ? o->fixed_outer : 0;
-  const int outer_max = fixed ? fixed : maxit;
-  int rc = ensure_workspace(h, A->n, 1, outer_max + 1, true);
-  if (rc) return rc;
-  Workspace &w = h->ws;
-  rc = state_init(h, 1, outer_max, fixed ? 1 : 0, rtol);
-  if (rc) return rc;
-  const Prec pc = prec_of(A);
-  rc = launch_op(h, A, x, EpiPcgInit{b, w.r, w.pcg_p, pc, w.hist}, 3);
-  if (rc) return rc;
-  const int every = (o && o->check_every > 0) ? o->check_every : 32;
-  const int G = grid_rows(A->n);
-  int k = 0;
-  rc = read_state(h, false);
-  if (rc) return rc;
-  while (k < outer_max && h->h_read->status == ST_RUNNING) {
-    const int m = std::min(every, outer_max - k);
-    for (int i = 0; i < m; ++i, ++k) {
-      rc = launch_op(h, A, w.pcg_p, EpiPcgSpmv{w.pcg_p, w.pcg_s}, 0);
-      if (rc) return rc;
-      prof_begin(h, 2);
-      k_pcg_update<<<G, kWG, 0, h->stream>>>(A->n, x, w.r, w.pcg_p, w.pcg_s, pc, h->st,
-                                             w.partials);
-      k_finalize<FinPcgUpdate><<<1, kWG, 0, h->stream>>>(FinPcgUpdate{w.hist}, h->st, w.partials,
-                                                         G);
-      prof_end(h);
-      LAUNCHCHK(h);
-      prof_begin(h, 2);
-      k_pcg_direction<<<G, kWG, 0, h->stream>>>(A->n, w.r, w.pcg_p, pc, h->st);
-      prof_end(h);
-      LAUNCHCHK(h);
-    }
-    rc = read_state(h, false);
-    if (rc) return rc;
-  }
-  return finish_solve(h, A, b, x, 1, outer_max);
-}
-
 int ssp_solve(ssp_handle *h, const ssp_matrix *A, const double *b, double *x, int s, double rtol,
               int maxit, const ssp_opts *opts) {
   if (!h) return SSP_EINVAL;
   int rc = check_matrix(h, A);
   if (rc) return rc;
   const int method = opts ? opts->method : SSP_METHOD_SSTEP;
+  const int precision = opts ? opts->precision : SSP_PRECISION_FP64;
   if (!b || !x) return fail(h, SSP_EINVAL, "ssp_solve: NULL vector");
   if (!(rtol >= 0.0) || maxit < 0) return fail(h, SSP_EINVAL, "ssp_solve: rtol must be >= 0 and maxit >= 0");
   if (method == SSP_METHOD_SSTEP && (s < 1 || s > SSP_SMAX || s > A->n))
     return fail(h, SSP_EINVAL, "ssp_solve: s out of range (s=" + std::to_string(s) + ")");
   if (method != SSP_METHOD_SSTEP && method != SSP_METHOD_PCG)
     return fail(h, SSP_EINVAL, "ssp_solve: unknown method " + std::to_string(method));
-  if (opts && opts->precision != SSP_PRECISION_FP64)
-    return fail(h, SSP_EUNSUPPORTED, "ssp_solve: precision " + std::to_string(opts->precision) + " not available");
+  if (precision != SSP_PRECISION_FP64 && precision != SSP_PRECISION_MIXED_IR)
+    return fail(h, SSP_EINVAL, "ssp_solve: unknown precision " + std::to_string(precision));
+  if (precision == SSP_PRECISION_MIXED_IR && method != SSP_METHOD_SSTEP)
+    return fail(h, SSP_EUNSUPPORTED, "ssp_solve: mixed precision is implemented for the s-step method");
   HIPCHK(h, hipSetDevice(h->device));
   h->prof_on = opts && opts->profile;
   h->ev_used = 0;
@@ -851,6 +817,8 @@ int ssp_solve(ssp_handle *h, const ssp_matrix *A, const double *b, double *x, in
     h->prof_launch[c] = 0;
     h->prof_ms[c] = 0.0;
   }
+  if (precision == SSP_PRECISION_MIXED_IR)
+    return solve_mixed(h, const_cast<ssp_matrix *>(A), b, x, s, rtol, maxit, opts);
   if (method == SSP_METHOD_PCG) return solve_pcg(h, A, b, x, rtol, maxit, opts);
   return solve_sstep(h, A, b, x, s, rtol, maxit, opts);
 }

@@ -33,7 +33,12 @@ struct DevState {
   int fixed;          // fixed-iteration mode: no stopping test
   int s;
   int hist_cap;
-  int pad0, pad1;
+  int ir_refine;      // iterative refinement: index of the current outer step
+  int ir_max_refine;
+  int ir_hist_cap;
+  int pad0;
+  double ir_bb;       // ||b||^2 of the FP64 system
+  double ir_rtol;     // outer (FP64) relative tolerance
   double bb;          // ||b||^2
   double rr;          // ||r||^2 after the latest update
   double rtol;

@@ -1,0 +1,277 @@
+// Host-side engine of libsstep: handle and matrix objects, workspaces, the
+// device control block, profiling, and the launch sequences of one outer
+// iteration.  Shared by the C-ABI translation unit and the per-precision
+// instantiation units (inst_f64.hip, inst_f32.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "sstep.h"
+
+namespace ssp {
+
+// Workspace of the solves of one handle (grown on demand, reused).
+struct Workspace {
+  int64_t n = 0, ld = 0;
+  int s = 0;
+  double *P1 = nullptr, *P2 = nullptr;     // n x 2s FP64 blocks, column-major, leading dim ld
+  double *r = nullptr;
+  double *pcg_p = nullptr, *pcg_s = nullptr;
+  int64_t n32 = 0, ld32 = 0;
+  int s32 = 0;
+  float *Q1 = nullptr, *Q2 = nullptr;       // FP32 blocks of the inner solves
+  float *r32 = nullptr, *d32 = nullptr;
+  double *partials = nullptr;              // kGridMax x 2*kSMax
+  double *hist = nullptr;
+  int hist_cap = 0;
+};
+
+}  // namespace ssp
+
+struct ssp_handle {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  ssp::Workspace ws;
+  ssp::DevState *st = nullptr;     // device control block
+  ssp::DevState *h_init = nullptr; // pinned staging for the control block
+  ssp::DevState *h_read = nullptr; // pinned readback
+  // results of the last solve
+  int last_outer = 0, last_s = 1;
+  double last_true_rel = NAN;
+  std::vector<double> last_hist;
+  // profiling (HIP events around launches)
+  bool prof_on = false;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> ev_cls;
+  std::vector<int> ev_iter;        // outer iteration of the launch (-1: outside the loop)
+  int prof_iter = -1;
+  size_t ev_used = 0;
+  int prof_launch[4] = {0, 0, 0, 0};
+  double prof_ms[4] = {0, 0, 0, 0};
+};
+
+struct ssp_matrix {
+  ssp_handle *h = nullptr;
+  int kind = 0;                    // 0 = CSR, else SSP_STENCIL_*
+  int64_t n = 0, nnz = 0;
+  ssp::CsrArgs<double> csr{};
+  ssp::CsrArgs<float> csr32{};     // FP32 values (built on first mixed-precision use)
+  int32_t *own_rowptr = nullptr, *own_colind = nullptr;
+  double *own_val = nullptr;
+  float *val32 = nullptr;
+  ssp::StencilArgs<double> sten{};
+  ssp::StencilArgs<float> sten32{};
+  float *k32 = nullptr;
+  double *dinv = nullptr;          // Jacobi vector (CSR, variable coefficient)
+  float *dinv32 = nullptr;
+  double dconst = 1.0;             // Jacobi constant (constant-diagonal stencils)
+  bool has32 = false;
+  int prec = SSP_PREC_JACOBI;
+};
+
+namespace ssp {
+
+inline int fail(ssp_handle *h, int code, const std::string &msg) {
+  if (h) h->err = msg;
+  return code;
+}
+
+#define HIPCHK(h, call)                                                               \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return ssp::fail((h), SSP_EHIP, std::string("HIP error ") + hipGetErrorString(e_) + \
+                                          " (line " + std::to_string(__LINE__) + ")"); \
+  } while (0)
+
+#define LAUNCHCHK(h) HIPCHK(h, hipGetLastError())
+
+template <typename T> struct Prec;
+
+inline Prec<double> prec_of(const ssp_matrix *A, double *) {
+  if (A->prec == SSP_PREC_NONE) return Prec<double>{nullptr, 1.0};
+  if (A->dinv) return Prec<double>{A->dinv, 0.0};
+  return Prec<double>{nullptr, A->dconst};
+}
+inline Prec<float> prec_of(const ssp_matrix *A, float *) {
+  if (A->prec == SSP_PREC_NONE) return Prec<float>{nullptr, 1.0f};
+  if (A->dinv32) return Prec<float>{A->dinv32, 0.0f};
+  return Prec<float>{nullptr, (float)A->dconst};
+}
+
+inline const CsrArgs<double> &csr_of(const ssp_matrix *A, double *) { return A->csr; }
+inline const CsrArgs<float> &csr_of(const ssp_matrix *A, float *) { return A->csr32; }
+inline const StencilArgs<double> &sten_of(const ssp_matrix *A, double *) { return A->sten; }
+inline const StencilArgs<float> &sten_of(const ssp_matrix *A, float *) { return A->sten32; }
+
+inline int grid_rows(int64_t n) {
+  int64_t g = (n + kWG - 1) / kWG;
+  if (g > kGridMax) g = kGridMax;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+inline int grid_of(const ssp_matrix *A) {
+  if (A->kind == 0 && A->csr.variant == CSR_STAGED) {
+    int64_t g = A->csr.nrb;
+    if (g > kGridMax) g = kGridMax;
+    return (int)std::max<int64_t>(g, 1);
+  }
+  return grid_rows(A->n);
+}
+
+// Profiling classes: 0 matrix powers j < s and plain SpMV, 1 last power with
+// moments and s x s solve, 2 vector/block updates, 3 other.
+inline void prof_begin(ssp_handle *h, int cls) {
+  if (!h->prof_on) return;
+  if (h->ev_used + 2 > h->ev.size()) {
+    for (int i = 0; i < 64; ++i) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return;
+      h->ev.push_back(e);
+    }
+    h->ev_cls.resize(h->ev.size() / 2 + 64);
+    h->ev_iter.resize(h->ev.size() / 2 + 64);
+  }
+  h->ev_cls[h->ev_used / 2] = cls;
+  h->ev_iter[h->ev_used / 2] = h->prof_iter;
+  (void)hipEventRecord(h->ev[h->ev_used], h->stream);
+}
+
+inline void prof_end(ssp_handle *h) {
+  if (!h->prof_on || h->ev_used + 2 > h->ev.size()) return;
+  (void)hipEventRecord(h->ev[h->ev_used + 1], h->stream);
+  h->ev_used += 2;
+}
+
+// Launches of iterations enqueued after the stop (no-op kernels) are skipped:
+// the averages describe launches that did the work.
+inline void prof_collect(ssp_handle *h, int iters_done) {
+  if (!h->prof_on) return;
+  for (size_t i = 0; i + 1 < h->ev_used; i += 2) {
+    if (h->ev_iter[i / 2] >= iters_done) continue;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, h->ev[i], h->ev[i + 1]) == hipSuccess) {
+      const int c = h->ev_cls[i / 2];
+      h->prof_launch[c] += 1;
+      h->prof_ms[c] += ms;
+    }
+  }
+  h->ev_used = 0;
+}
+
+// Operator launch (CSR or stencil kind) with epilogue Epi, followed by the
+// finalisation kernel when Epi reduces.
+template <typename T, class Epi>
+int launch_op(ssp_handle *h, const ssp_matrix *A, const T *x, const Epi &epi, int cls) {
+  const int G = grid_of(A);
+  T *tag = nullptr;
+  prof_begin(h, cls);
+  switch (A->kind) {
+    case 0:
+      k_csr<T, Epi><<<G, kWG, 0, h->stream>>>(csr_of(A, tag), x, epi, h->st, h->ws.partials);
+      break;
+    case SSP_STENCIL_2D5:
+      k_stencil<K_2D5, T, Epi><<<G, kWG, 0, h->stream>>>(sten_of(A, tag), x, epi, h->st,
+                                                          h->ws.partials);
+      break;
+    case SSP_STENCIL_3D7:
+      k_stencil<K_3D7, T, Epi><<<G, kWG, 0, h->stream>>>(sten_of(A, tag), x, epi, h->st,
+                                                          h->ws.partials);
+      break;
+    case SSP_STENCIL_3D27:
+      k_stencil<K_3D27, T, Epi><<<G, kWG, 0, h->stream>>>(sten_of(A, tag), x, epi, h->st,
+                                                           h->ws.partials);
+      break;
+    case SSP_STENCIL_3D7_VARK:
+      k_stencil<K_VARK, T, Epi><<<G, kWG, 0, h->stream>>>(sten_of(A, tag), x, epi, h->st,
+                                                           h->ws.partials);
+      break;
+    default:
+      return fail(h, SSP_EINVAL, "unknown operator kind " + std::to_string(A->kind));
+  }
+  if constexpr (Epi::NP > 0) {
+    k_finalize<Epi><<<1, kWG, 0, h->stream>>>(epi, h->st, h->ws.partials, G);
+  }
+  prof_end(h);
+  LAUNCHCHK(h);
+  return SSP_OK;
+}
+
+// Blocks and vectors of one outer iteration in precision T.
+template <typename T>
+struct IterBufs {
+  T *P1, *P2;       // ping-pong n x 2s blocks
+  int64_t ld;
+  T *x, *r;
+};
+
+// One outer iteration of the s-step method (Alg. 3): s matrix-power
+// launches (Alg. 4; the last fused with Alg. 5 and followed by the s x s
+// solve of Alg. 6 on the GPU) and the fused block update.
+template <int S, typename T>
+int sstep_iteration(ssp_handle *h, const ssp_matrix *A, const IterBufs<T> &B, int k) {
+  T *Pc = (k % 2 == 0) ? B.P2 : B.P1;   // Alg. 3: even k fills P2, odd k fills P1
+  T *Po = (k % 2 == 0) ? B.P1 : B.P2;
+  T *tag = nullptr;
+  const Prec<T> pc = prec_of(A, tag);
+  for (int j = 1; j <= S; ++j) {
+    const T *zin = Pc + (int64_t)(j - 1) * B.ld;
+    T *az = Pc + (int64_t)(S + j - 1) * B.ld;
+    int rc;
+    if (j < S) rc = launch_op<T>(h, A, zin, EpiMpk<T>{az, Pc + (int64_t)j * B.ld, pc}, 0);
+    else rc = launch_op<T>(h, A, zin, EpiMpkLast<S, T>{az, Pc, B.ld, B.r, 1}, 1);
+    if (rc) return rc;
+  }
+  const int G = grid_rows(A->n);
+  prof_begin(h, 2);
+  k_update<S, T><<<G, kWG, 0, h->stream>>>(A->n, B.ld, Pc, Po, B.x, B.r, pc, h->st,
+                                            h->ws.partials);
+  k_finalize<FinUpdate><<<1, kWG, 0, h->stream>>>(FinUpdate{h->ws.hist}, h->st, h->ws.partials,
+                                                  G);
+  prof_end(h);
+  LAUNCHCHK(h);
+  return SSP_OK;
+}
+
+// Alg. 4 + Alg. 5 on their own (no solve): the block P and vm in the state.
+template <int S>
+int mpk_only(ssp_handle *h, const ssp_matrix *A, const double *r, double *P, int64_t ld) {
+  double *tag = nullptr;
+  const Prec<double> pc = prec_of(A, tag);
+  const int G = grid_rows(A->n);
+  k_prec<double><<<G, kWG, 0, h->stream>>>(A->n, r, P, pc);
+  LAUNCHCHK(h);
+  for (int j = 1; j <= S; ++j) {
+    const double *zin = P + (int64_t)(j - 1) * ld;
+    double *az = P + (int64_t)(S + j - 1) * ld;
+    int rc;
+    if (j < S) rc = launch_op<double>(h, A, zin, EpiMpk<double>{az, P + (int64_t)j * ld, pc}, 0);
+    else rc = launch_op<double>(h, A, zin, EpiMpkLast<S, double>{az, P, ld, r, 0}, 1);
+    if (rc) return rc;
+  }
+  return SSP_OK;
+}
+
+template <typename T>
+using iter_fn = int (*)(ssp_handle *, const ssp_matrix *, const IterBufs<T> &, int);
+using mpk_fn = int (*)(ssp_handle *, const ssp_matrix *, const double *, double *, int64_t);
+
+// Defined in inst_f64.hip (s = 1..16) and inst_f32.hip (s = 1..8);
+// nullptr for an s out of range.
+iter_fn<double> iteration_f64(int s);
+iter_fn<float> iteration_f32(int s);
+mpk_fn mpk_f64(int s);
+
+constexpr int kSMaxF32 = 8;
+
+}  // namespace ssp

@@ -1,0 +1,233 @@
+// Operator application on gfx950: CSR (two kernel forms) and matrix-free
+// grid stencils, in FP64 or FP32.  Each visitor walks a range of rows and
+// hands (row, (A x)_row) to a functor that runs in the thread owning the row.
+//
+// Rounding: products are rounded, then summed in the order of the stored
+// columns (CSR) or of the stencil definition (matrix-free); FMA contraction
+// is off, so the FP64 results are bitwise equal to a plain sequential
+// evaluation of the same definition.
+#pragma once
+
+#include "common.hpp"
+
+namespace ssp {
+
+enum : int { CSR_STAGED = 0, CSR_ROW = 1 };
+enum : int { K_2D5 = 1, K_3D7 = 2, K_3D27 = 3, K_VARK = 4 };
+
+template <typename T>
+struct CsrArgs {
+  int64_t n;
+  const int32_t *rowptr;
+  const int32_t *colind;
+  const T *val;
+  int rows_per_rb;   // rows per LDS row block (CSR_STAGED, <= kCsrRowsMax)
+  int64_t nrb;       // number of row blocks
+  int variant;       // CSR_STAGED or CSR_ROW, chosen per matrix by timing
+};
+
+template <typename T>
+struct StencilArgs {
+  int64_t n;
+  int nx, ny, nz;
+  FastDiv fx, fy;    // divisions by nx and ny
+  T diag, off;
+  const T *k;        // cell coefficients (variable-coefficient kind)
+};
+
+// Jacobi (or identity) preconditioner: z = dinv .* v.
+template <typename T>
+struct Prec {
+  const T *dinv;     // nullptr: the constant dc
+  T dc;
+  __device__ __forceinline__ T apply(int64_t i, T v) const {
+#pragma clang fp contract(off)
+    return (dinv ? dinv[i] : dc) * v;
+  }
+};
+
+// Rows of one CSR row block (at most kCsrLds stored entries) are staged as
+// products val*x in LDS: every thread first issues all its coalesced loads of
+// colind and val, then all its gathers of x, so each workgroup keeps up to
+// kCsrLds/kWG independent loads in flight.  Each thread then sums its rows in
+// column order.  Rows longer than the staging buffer fall back to a direct
+// per-thread loop.  Walks row blocks [rb0, rb1); all threads must call it.
+template <typename T, class F>
+__device__ __forceinline__ void csr_rows_staged(const CsrArgs<T> &A, const T *__restrict__ x,
+                                                int64_t rb0, int64_t rb1, F &&f) {
+#pragma clang fp contract(off)
+  constexpr int kPer = kCsrLds / kWG;
+  __shared__ T prod[kCsrLds];
+  for (int64_t rb = rb0; rb < rb1; ++rb) {
+    const int64_t r0 = rb * A.rows_per_rb;
+    const int64_t r1 = (r0 + A.rows_per_rb < A.n) ? r0 + A.rows_per_rb : A.n;
+    const int e0 = A.rowptr[r0];
+    const int cnt = A.rowptr[r1] - e0;
+    if (cnt <= kCsrLds) {
+      int ci[kPer];
+      T vv[kPer];
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const int e = threadIdx.x + u * kWG;
+        if (e < cnt) {
+          ci[u] = A.colind[e0 + e];
+          vv[u] = A.val[e0 + e];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const int e = threadIdx.x + u * kWG;
+        if (e < cnt) vv[u] = vv[u] * x[ci[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const int e = threadIdx.x + u * kWG;
+        if (e < cnt) prod[e] = vv[u];
+      }
+      __syncthreads();
+      for (int64_t row = r0 + threadIdx.x; row < r1; row += kWG) {
+        const int a = A.rowptr[row] - e0, b = A.rowptr[row + 1] - e0;
+        T acc = 0;
+        for (int e = a; e < b; ++e) acc += prod[e];
+        f(row, acc);
+      }
+      __syncthreads();
+    } else {
+      for (int64_t row = r0 + threadIdx.x; row < r1; row += kWG) {
+        T acc = 0;
+        for (int e = A.rowptr[row]; e < A.rowptr[row + 1]; ++e) {
+          const T t = A.val[e] * x[A.colind[e]];
+          acc += t;
+        }
+        f(row, acc);
+      }
+    }
+  }
+}
+
+// One thread per row over rows [r0, r1) (consecutive rows in consecutive
+// threads): each thread issues the loads of up to 8 stored entries of its row
+// at once, then their gathers, then sums in column order.  No LDS, no
+// barriers; suits short rows.
+template <typename T, class F>
+__device__ __forceinline__ void csr_rows_direct(const CsrArgs<T> &A, const T *__restrict__ x,
+                                                int64_t r0, int64_t r1, F &&f) {
+#pragma clang fp contract(off)
+  constexpr int U = 8;
+  for (int64_t row = r0 + threadIdx.x; row < r1; row += kWG) {
+    const int a = A.rowptr[row], b = A.rowptr[row + 1];
+    T acc = 0;
+    for (int e = a; e < b; e += U) {
+      int ci[U];
+      T vv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (e + u < b) {
+          ci[u] = A.colind[e + u];
+          vv[u] = A.val[e + u];
+        }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (e + u < b) vv[u] = vv[u] * x[ci[u]];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (e + u < b) acc += vv[u];
+    }
+    f(row, acc);
+  }
+}
+
+// The workgroup's share of a whole-matrix product (contiguous chunk).
+template <typename T, class F>
+__device__ __forceinline__ void csr_rows(const CsrArgs<T> &A, const T *__restrict__ x, F &&f) {
+  if (A.variant == CSR_ROW) {
+    int64_t r0, r1;
+    block_chunk(A.n, logical_block(), gridDim.x, r0, r1);
+    csr_rows_direct(A, x, r0, r1, f);
+  } else {
+    int64_t rb0, rb1;
+    block_chunk(A.nrb, logical_block(), gridDim.x, rb0, rb1);
+    csr_rows_staged(A, x, rb0, rb1, f);
+  }
+}
+
+// Harmonic mean of two cell coefficients: the face weight of the
+// variable-coefficient 7-point operator for -div(k grad u).
+template <typename T>
+__device__ __forceinline__ T face_weight(T kp, T kq) {
+#pragma clang fp contract(off)
+  const T num = T(2) * kp * kq;
+  return num / (kp + kq);
+}
+
+// Matrix-free grid operators over points [p0, p1); neighbour order follows
+// the definitions (Dirichlet: neighbours outside the grid are absent).
+template <int KIND, typename T, class F>
+__device__ __forceinline__ void stencil_rows(const StencilArgs<T> &S, const T *__restrict__ x,
+                                             int64_t p0, int64_t p1, F &&f) {
+#pragma clang fp contract(off)
+  const int nx = S.nx, ny = S.ny, nz = S.nz;
+  const int64_t sy = nx, sz = (int64_t)nx * ny;
+  for (int64_t p = p0 + threadIdx.x; p < p1; p += kWG) {
+    int64_t rx, ry;
+    const int64_t yz = fdiv(p, S.fx, rx);
+    const int64_t zq = fdiv(yz, S.fy, ry);
+    const int xq = (int)rx, yq = (int)ry, z = (int)zq;
+    T acc;
+    if constexpr (KIND == K_3D27) {
+      T nb = 0;
+      for (int dz = -1; dz <= 1; ++dz) {
+        const int qz = z + dz;
+        if (qz < 0 || qz >= nz) continue;
+        for (int dy = -1; dy <= 1; ++dy) {
+          const int qy = yq + dy;
+          if (qy < 0 || qy >= ny) continue;
+          const T *row = x + (int64_t)qz * sz + (int64_t)qy * sy;
+          for (int dx = -1; dx <= 1; ++dx) {
+            const int qx = xq + dx;
+            if (qx < 0 || qx >= nx) continue;
+            if (dx == 0 && dy == 0 && dz == 0) continue;
+            nb += row[qx];
+          }
+        }
+      }
+      const T d = S.diag * x[p];
+      const T o = S.off * nb;
+      acc = d + o;
+    } else if constexpr (KIND == K_VARK) {
+      const T kp = S.k[p];
+      const bool in[6] = {z > 0, yq > 0, xq > 0, xq < nx - 1, yq < ny - 1, z < nz - 1};
+      const int64_t q[6] = {p - sz, p - sy, p - 1, p + 1, p + sy, p + sz};
+      T dsum = 0, nb = 0;
+#pragma unroll
+      for (int f6 = 0; f6 < 6; ++f6) {
+        if (in[f6]) {
+          const T w = face_weight(kp, S.k[q[f6]]);
+          dsum += w;
+          const T t = w * x[q[f6]];
+          nb += t;
+        } else {
+          dsum += kp;
+        }
+      }
+      const T d = dsum * x[p];
+      acc = d - nb;
+    } else {
+      T nb = 0;
+      if (xq > 0) nb += x[p - 1];
+      if (xq < nx - 1) nb += x[p + 1];
+      if (yq > 0) nb += x[p - sy];
+      if (yq < ny - 1) nb += x[p + sy];
+      if constexpr (KIND == K_3D7) {
+        if (z > 0) nb += x[p - sz];
+        if (z < nz - 1) nb += x[p + sz];
+      }
+      const T d = S.diag * x[p];
+      const T o = S.off * nb;
+      acc = d + o;
+    }
+    f(p, acc);
+  }
+}
+
+}  // namespace ssp

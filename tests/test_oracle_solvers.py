@@ -80,6 +80,20 @@ def test_exact_sstep_iterates_equal_pcg_every_s_steps(name, s):
         assert all(W[i][j] == W[j][i] for i in range(s) for j in range(s))
 
 
+@pytest.mark.parametrize("s", [2, 3, 4])
+def test_printed_b1_bound_breaks_equivalence(s):
+    """With the inner loop bound of Alg. 6 read literally (j = 1..i-1), part
+    of P_{i-1}^T A Z_i is dropped and the iterates leave the PCG ones; the
+    full-range reading keeps them equal (previous test)."""
+    A = _tridiag(PROBLEMS["varcoef1d"])
+    n = len(A)
+    b = [(-1) ** i * (i % 5 + 1) for i in range(n)]
+    bdiag = [A[i][i] for i in range(n)]
+    ref = exact.pcg(A, b, bdiag, n)
+    got = exact.sstep(A, b, bdiag, s, 2, b1_printed_bound=True)
+    assert got["x"][2] != ref[2 * s]
+
+
 @pytest.mark.parametrize("name", list(PROBLEMS))
 @pytest.mark.parametrize("s", [1, 2, 3, 4])
 def test_c_oracle_matches_exact_arithmetic(name, s):
