@@ -198,6 +198,46 @@ int ssp_get_true_residual(const ssp_handle *h, double *rel);
  * 3 = other (initial and true residual). */
 int ssp_get_profile(const ssp_handle *h, int *launches, double *ms);
 
+/* ---- batched solves ---------------------------------------------------------- */
+
+/* Tuning of the batched persistent solver (all fields 0 = default). */
+typedef struct ssp_tune {
+  int tile_rows;       /* rows per work item; 0 = the row partition of a single
+                          solve, so that every system's result equals its
+                          ssp_solve (MIXED_IR) result bit for bit           */
+  int grid;            /* persistent workgroups (default 512)                 */
+  int order;           /* 0 = idle workgroups look at the largest systems
+                          first; 1 = round-robin start per workgroup          */
+  int spin_limit;      /* consecutive empty polls without global progress
+                          after which the launch gives up (default 2^20)      */
+} ssp_tune;
+
+/* Solves nsys independent systems A[i] x[i] = b[i] in ONE persistent launch
+ * (the batch extension of the method): each system runs the mixed-precision
+ * form of the s-step method (FP32 matrix powers and block updates, FP64
+ * moments, s x s solves, residuals and refinement; opts->inner_rtol and
+ * opts->max_refine as for ssp_solve, opts->precision is ignored), with its
+ * own phase state machine; workgroups take tiles of rows from any system
+ * with work ready.  A, b, x are HOST arrays of nsys matrix handles / DEVICE
+ * vector pointers (x in: x0, out: solution).  1 <= s <= 8, s <= every n.
+ * Per-system outcome codes, inner outer-iteration counts and true relative
+ * residuals go to the optional HOST arrays status_out, outer_out,
+ * true_rel_out.  Returns the worst per-system outcome (SSP_OK,
+ * SSP_NOT_CONVERGED, SSP_BREAKDOWN) or a negative error (SSP_EHIP if the
+ * scheduler stalled). */
+int ssp_solve_batch(ssp_handle *h, int nsys, const ssp_matrix *const *A,
+                    const double *const *b, double *const *x, int s, double rtol,
+                    int maxit, const ssp_opts *opts, const ssp_tune *tune,
+                    int *status_out, int *outer_out, double *true_rel_out);
+
+/* Chooses tile size, grid size and scan order for a batch by timing short
+ * runs of ssp_solve_batch on scratch iterates; with a non-NULL cache_path the
+ * choice is read from / appended to that text file, keyed by architecture,
+ * batch size, total rows (log2), s and operator kinds. */
+int ssp_autotune_batch(ssp_handle *h, int nsys, const ssp_matrix *const *A,
+                       const double *const *b, int s, const char *cache_path,
+                       ssp_tune *out);
+
 /* Text for a status code (static storage). */
 const char *ssp_status_string(int status);
 

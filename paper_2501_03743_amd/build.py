@@ -16,9 +16,9 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libsstep.so")
-SOURCES = ["capi.hip", "inst_f64.hip", "inst_f32.hip"]
+SOURCES = ["capi.hip", "inst_f64.hip", "inst_f32.hip", "batch.hip"]
 HEADERS = ["common.hpp", "operators.hpp", "small_solve.hpp", "kernels.hpp",
-           "setup_kernels.hpp", "engine.hpp"]
+           "setup_kernels.hpp", "engine.hpp", "batch.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -7,6 +7,62 @@
 
 using namespace ssp;
 
+namespace ssp {
+
+int status_code(int st) {
+  switch (st) {
+    case ST_CONVERGED:
+    case ST_ZERO_RHS:
+      return SSP_OK;
+    case ST_BREAKDOWN:
+      return SSP_BREAKDOWN;
+    default:
+      return SSP_NOT_CONVERGED;
+  }
+}
+
+// Builds the FP32 copy of a matrix (values, coefficients, Jacobi vector).
+int ensure_fp32(ssp_handle *h, ssp_matrix *A) {
+  if (A->has32) return SSP_OK;
+  const unsigned nb = (unsigned)((A->n + kWG - 1) / kWG);
+  if (A->kind == 0) {
+    if (hipMalloc(&A->val32, sizeof(float) * A->nnz) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(h, SSP_ENOMEM, "FP32 matrix allocation failed");
+    }
+    const unsigned nbz = (unsigned)((A->nnz + kWG - 1) / kWG);
+    k_to_float<<<nbz, kWG, 0, h->stream>>>(A->nnz, A->csr.val, A->val32);
+    LAUNCHCHK(h);
+    A->csr32 = CsrArgs<float>{A->csr.n, A->csr.rowptr, A->csr.colind, A->val32,
+                              A->csr.rows_per_rb, A->csr.nrb, A->csr.variant};
+  } else {
+    const StencilArgs<double> &S = A->sten;
+    A->sten32 = StencilArgs<float>{S.n, S.nx, S.ny, S.nz, S.fx, S.fy, (float)S.diag,
+                                   (float)S.off, nullptr};
+    if (A->kind == SSP_STENCIL_3D7_VARK) {
+      if (hipMalloc(&A->k32, sizeof(float) * A->n) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(h, SSP_ENOMEM, "FP32 coefficient allocation failed");
+      }
+      k_to_float<<<nb, kWG, 0, h->stream>>>(A->n, S.k, A->k32);
+      LAUNCHCHK(h);
+      A->sten32.k = A->k32;
+    }
+  }
+  if (A->dinv) {
+    if (hipMalloc(&A->dinv32, sizeof(float) * A->n) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(h, SSP_ENOMEM, "FP32 Jacobi allocation failed");
+    }
+    k_to_float<<<nb, kWG, 0, h->stream>>>(A->n, A->dinv, A->dinv32);
+    LAUNCHCHK(h);
+  }
+  A->has32 = true;
+  return SSP_OK;
+}
+
+}  // namespace ssp
+
 namespace {
 
 void hfree(void *&p) {
@@ -126,18 +182,6 @@ int check_matrix(ssp_handle *h, const ssp_matrix *A) {
   return SSP_OK;
 }
 
-int status_code(int st) {
-  switch (st) {
-    case ST_CONVERGED:
-    case ST_ZERO_RHS:
-      return SSP_OK;
-    case ST_BREAKDOWN:
-      return SSP_BREAKDOWN;
-    default:
-      return SSP_NOT_CONVERGED;
-  }
-}
-
 // The true residual of the returned iterate and the results of the solve.
 int finish_solve(ssp_handle *h, const ssp_matrix *A, const double *b, double *x, int s) {
   int rc = read_state(h, false);
@@ -162,46 +206,6 @@ int finish_solve(ssp_handle *h, const ssp_matrix *A, const double *b, double *x,
     HIPCHK(h, hipMemcpy(h->last_hist.data(), h->ws.hist, sizeof(double) * len,
                         hipMemcpyDeviceToHost));
   return status_code(status);
-}
-
-// Builds the FP32 copy of a matrix (values, coefficients, Jacobi vector).
-int ensure_fp32(ssp_handle *h, ssp_matrix *A) {
-  if (A->has32) return SSP_OK;
-  const unsigned nb = (unsigned)((A->n + kWG - 1) / kWG);
-  if (A->kind == 0) {
-    if (hipMalloc(&A->val32, sizeof(float) * A->nnz) != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(h, SSP_ENOMEM, "FP32 matrix allocation failed");
-    }
-    const unsigned nbz = (unsigned)((A->nnz + kWG - 1) / kWG);
-    k_to_float<<<nbz, kWG, 0, h->stream>>>(A->nnz, A->csr.val, A->val32);
-    LAUNCHCHK(h);
-    A->csr32 = CsrArgs<float>{A->csr.n, A->csr.rowptr, A->csr.colind, A->val32,
-                              A->csr.rows_per_rb, A->csr.nrb, A->csr.variant};
-  } else {
-    const StencilArgs<double> &S = A->sten;
-    A->sten32 = StencilArgs<float>{S.n, S.nx, S.ny, S.nz, S.fx, S.fy, (float)S.diag,
-                                   (float)S.off, nullptr};
-    if (A->kind == SSP_STENCIL_3D7_VARK) {
-      if (hipMalloc(&A->k32, sizeof(float) * A->n) != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(h, SSP_ENOMEM, "FP32 coefficient allocation failed");
-      }
-      k_to_float<<<nb, kWG, 0, h->stream>>>(A->n, S.k, A->k32);
-      LAUNCHCHK(h);
-      A->sten32.k = A->k32;
-    }
-  }
-  if (A->dinv) {
-    if (hipMalloc(&A->dinv32, sizeof(float) * A->n) != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(h, SSP_ENOMEM, "FP32 Jacobi allocation failed");
-    }
-    k_to_float<<<nb, kWG, 0, h->stream>>>(A->n, A->dinv, A->dinv32);
-    LAUNCHCHK(h);
-  }
-  A->has32 = true;
-  return SSP_OK;
 }
 
 // Both CSR kernels give bitwise-identical products; pick the faster one for
@@ -538,6 +542,7 @@ int ssp_destroy(ssp_handle *h) {
   hfree_t(w.partials);
   hfree_t(w.hist);
   hfree_t(h->st);
+  if (h->batch_mem) (void)hipFree(h->batch_mem);
   if (h->h_init) (void)hipHostFree(h->h_init);
   if (h->h_read) (void)hipHostFree(h->h_read);
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);

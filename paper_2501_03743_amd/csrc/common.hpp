@@ -36,7 +36,7 @@ struct DevState {
   int ir_refine;      // iterative refinement: index of the current outer step
   int ir_max_refine;
   int ir_hist_cap;
-  int pad0;
+  int ir_inner_total; // batched solves: inner outer iterations over all refinements
   double ir_bb;       // ||b||^2 of the FP64 system
   double ir_rtol;     // outer (FP64) relative tolerance
   double bb;          // ||b||^2

@@ -57,6 +57,9 @@ struct ssp_handle {
   size_t ev_used = 0;
   int prof_launch[4] = {0, 0, 0, 0};
   double prof_ms[4] = {0, 0, 0, 0};
+  // batched solves: one device buffer for every per-system array
+  void *batch_mem = nullptr;
+  size_t batch_bytes = 0;
 };
 
 struct ssp_matrix {
@@ -273,5 +276,9 @@ iter_fn<float> iteration_f32(int s);
 mpk_fn mpk_f64(int s);
 
 constexpr int kSMaxF32 = 8;
+
+// Shared helpers defined in capi.hip.
+int ensure_fp32(ssp_handle *h, ssp_matrix *A);
+int status_code(int device_status);
 
 }  // namespace ssp

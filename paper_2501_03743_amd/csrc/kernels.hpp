@@ -285,25 +285,30 @@ __global__ __launch_bounds__(kWG) void k_stencil(StencilArgs<T> S, const T *__re
 // ||r||^2 (finished by FinUpdate).  With T = float the new P and AP are
 // rounded to FP32 before they update x and r, as stored.
 template <int S, typename T>
-__global__ __launch_bounds__(kWG) void k_update(int64_t n, int64_t ld, T *__restrict__ Pc,
-                                                T *__restrict__ Po, T *__restrict__ x,
-                                                T *__restrict__ r, Prec<T> pc, DevState *st,
-                                                double *partials) {
-#pragma clang fp contract(off)
-  if (st->status != ST_RUNNING) return;
-  const int k = st->k;
+struct UpdateCoef {
+  int k;
   double alpha[S], beta[S][S];
+  __device__ __forceinline__ void load(const DevState *st) {
+    k = st->k;
 #pragma unroll
-  for (int j = 0; j < S; ++j) alpha[j] = st->alpha[j];
-  if (k > 0) {
+    for (int j = 0; j < S; ++j) alpha[j] = st->alpha[j];
+    if (k > 0) {
 #pragma unroll
-    for (int l = 0; l < S; ++l)
+      for (int l = 0; l < S; ++l)
 #pragma unroll
-      for (int j = 0; j < S; ++j) beta[l][j] = st->beta[l * S + j];
+        for (int j = 0; j < S; ++j) beta[l][j] = st->beta[l * S + j];
+    }
   }
+};
+
+// The rows [lo, hi) of the block update; returns this thread's partial ||r||^2.
+template <int S, typename T>
+__device__ __forceinline__ double update_rows(const UpdateCoef<S, T> &c, int64_t lo, int64_t hi,
+                                              int64_t ld, T *__restrict__ Pc,
+                                              T *__restrict__ Po, T *__restrict__ x,
+                                              T *__restrict__ r, const Prec<T> &pc) {
+#pragma clang fp contract(off)
   double part = 0.0;
-  int64_t lo, hi;
-  block_chunk(n, logical_block(), gridDim.x, lo, hi);
   for (int64_t i = lo + threadIdx.x; i < hi; i += kWG) {
     double p[S], ap[S];
 #pragma unroll
@@ -311,7 +316,7 @@ __global__ __launch_bounds__(kWG) void k_update(int64_t n, int64_t ld, T *__rest
       p[j] = (double)Pc[(int64_t)j * ld + i];
       ap[j] = (double)Pc[(int64_t)(S + j) * ld + i];
     }
-    if (k > 0) {
+    if (c.k > 0) {
       double po[S], apo[S];
 #pragma unroll
       for (int l = 0; l < S; ++l) {
@@ -323,9 +328,9 @@ __global__ __launch_bounds__(kWG) void k_update(int64_t n, int64_t ld, T *__rest
         double a = p[j], b = ap[j];
 #pragma unroll
         for (int l = 0; l < S; ++l) {
-          const double t = po[l] * beta[l][j];
+          const double t = po[l] * c.beta[l][j];
           a += t;
-          const double u = apo[l] * beta[l][j];
+          const double u = apo[l] * c.beta[l][j];
           b += u;
         }
         const T as = (T)a, bs = (T)b;
@@ -338,9 +343,9 @@ __global__ __launch_bounds__(kWG) void k_update(int64_t n, int64_t ld, T *__rest
     double dx = 0.0, dr = 0.0;
 #pragma unroll
     for (int j = 0; j < S; ++j) {
-      const double t = p[j] * alpha[j];
+      const double t = p[j] * c.alpha[j];
       dx += t;
-      const double u = ap[j] * alpha[j];
+      const double u = ap[j] * c.alpha[j];
       dr += u;
     }
     const T xi = (T)((double)x[i] + dx);
@@ -350,7 +355,20 @@ __global__ __launch_bounds__(kWG) void k_update(int64_t n, int64_t ld, T *__rest
     Po[i] = pc.apply(i, ri);
     part += (double)ri * (double)ri;
   }
-  double v[1] = {part};
+  return part;
+}
+
+template <int S, typename T>
+__global__ __launch_bounds__(kWG) void k_update(int64_t n, int64_t ld, T *__restrict__ Pc,
+                                                T *__restrict__ Po, T *__restrict__ x,
+                                                T *__restrict__ r, Prec<T> pc, DevState *st,
+                                                double *partials) {
+  if (st->status != ST_RUNNING) return;
+  UpdateCoef<S, T> c;
+  c.load(st);
+  int64_t lo, hi;
+  block_chunk(n, logical_block(), gridDim.x, lo, hi);
+  double v[1] = {update_rows<S, T>(c, lo, hi, ld, Pc, Po, x, r, pc)};
   block_store_sums<1>(v, partials + blockIdx.x, gridDim.x);
 }
 

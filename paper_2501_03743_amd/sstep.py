@@ -34,7 +34,8 @@ EXPORTS = (
     "ssp_matrix_csr_from_stencil", "ssp_matrix_info", "ssp_matrix_csr_arrays",
     "ssp_matrix_destroy", "ssp_set_preconditioner", "ssp_spmv", "ssp_mpk", "ssp_solve",
     "ssp_get_iterations", "ssp_get_residual_history", "ssp_get_true_residual",
-    "ssp_get_profile", "ssp_status_string", "ssp_last_error",
+    "ssp_get_profile", "ssp_status_string", "ssp_last_error", "ssp_solve_batch",
+    "ssp_autotune_batch",
 )
 
 
@@ -42,6 +43,15 @@ class SspError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__("%s (%d): %s" % (status_string(code), code, msg))
         self.code = code
+
+
+class Tune(C.Structure):
+    """Batched-solver tuning (ssp_tune): tile_rows, grid, order, spin_limit."""
+    _fields_ = [("tile_rows", C.c_int), ("grid", C.c_int), ("order", C.c_int),
+                ("spin_limit", C.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class _Opts(C.Structure):
@@ -92,6 +102,9 @@ def load():
         "ssp_get_residual_history": (i32, [vp, vp, i32, C.POINTER(i32)]),
         "ssp_get_true_residual": (i32, [vp, C.POINTER(dbl)]),
         "ssp_get_profile": (i32, [vp, vp, vp]),
+        "ssp_solve_batch": (i32, [vp, i32, vp, vp, vp, i32, dbl, i32, C.POINTER(_Opts),
+                                  C.POINTER(Tune), vp, vp, vp]),
+        "ssp_autotune_batch": (i32, [vp, i32, vp, vp, i32, C.c_char_p, C.POINTER(Tune)]),
         "ssp_status_string": (C.c_char_p, [i32]),
         "ssp_last_error": (C.c_char_p, [vp]),
     }
@@ -299,6 +312,50 @@ class Handle:
         if rc:
             self._err(rc, "ssp_mpk")
         return P, vm
+
+    # ---------------------------------------------------------------- batches
+    def _batch_arrays(self, mats, bs, xs=None):
+        import torch
+        m = len(mats)
+        A = (C.c_void_p * m)(*[M._p for M in mats])
+        for t in bs:
+            _check_dev(t, torch.float64, name="b")
+        B = (C.c_void_p * m)(*[_ptr(t) for t in bs])
+        X = None
+        if xs is not None:
+            for M, t in zip(mats, xs):
+                _check_dev(t, torch.float64, M.n, name="x")
+            X = (C.c_void_p * m)(*[_ptr(t) for t in xs])
+        return m, A, B, X
+
+    def solve_batch(self, mats, bs, xs, s=4, rtol=1e-8, maxit=10000, inner_rtol=1e-5,
+                    max_refine=10, tune=None):
+        """One persistent launch over all systems (mixed-precision s-step).
+        Returns (worst status, per-system status, inner outer iterations,
+        true relative residuals)."""
+        m, A, B, X = self._batch_arrays(mats, bs, xs)
+        o = _Opts(method=0, precision=PRECISION["mixed_ir"], inner_rtol=inner_rtol,
+                  max_refine=max_refine)
+        st = np.zeros(m, dtype=np.int32)
+        it = np.zeros(m, dtype=np.int32)
+        tr = np.zeros(m)
+        rc = load().ssp_solve_batch(self._h, m, A, B, X, s, rtol, maxit, C.byref(o),
+                                    C.byref(tune) if tune is not None else None,
+                                    st.ctypes.data_as(C.c_void_p), it.ctypes.data_as(C.c_void_p),
+                                    tr.ctypes.data_as(C.c_void_p))
+        if rc < 0:
+            self._err(rc, "ssp_solve_batch")
+        return rc, st, it, tr
+
+    def autotune_batch(self, mats, bs, s=4, cache_path=None) -> Tune:
+        m, A, B, _ = self._batch_arrays(mats, bs)
+        out = Tune()
+        rc = load().ssp_autotune_batch(self._h, m, A, B, s,
+                                       cache_path.encode() if cache_path else None,
+                                       C.byref(out))
+        if rc < 0:
+            self._err(rc, "ssp_autotune_batch")
+        return out
 
     # ---------------------------------------------------------------- solve
     def solve(self, A: Matrix, b, x, s: int = 4, rtol: float = 1e-8, maxit: int = 10000,
