@@ -257,6 +257,8 @@ def main():
                    "fp64_ref_true_rel": rref.true_rel,
                    "sstep_fp64": run2(s=S),
                    "sstep_mixed_ir": run2(s=S, precision="mixed_ir"),
+                   "sstep_mixed_ir_inner1e-6": run2(s=S, precision="mixed_ir", inner_rtol=1e-6),
+                   "sstep_mixed_ir_inner1e-4": run2(s=S, precision="mixed_ir", inner_rtol=1e-4),
                    "pcg_fp64": run2(method="pcg")}
         A2.close()
         del b2, x2, xref

@@ -157,6 +157,7 @@ int ssp_solve_batch(ssp_handle *h, int nsys, const ssp_matrix *const *A, const d
     c.ir_max_refine = max_refine;
     c.ir_hist_cap = max_refine + 1;
     c.ir_rtol = rtol;
+    c.ir_inner_rtol = inner_rtol;
     BatchSched &q = sched[i];
     memset(&q, 0, sizeof(q));
     q.claim = 1ull << 32;   // sequence 1, tile 0

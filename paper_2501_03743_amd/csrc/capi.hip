@@ -426,6 +426,7 @@ int solve_mixed(ssp_handle *h, ssp_matrix *A, const double *b, double *x, int s,
     c->ir_max_refine = max_refine;
     c->ir_hist_cap = w.hist_cap;
     c->ir_rtol = rtol;
+    c->ir_inner_rtol = inner_rtol;
     HIPCHK(h, hipMemcpyAsync(h->st, c, offsetof(DevState, vm), hipMemcpyHostToDevice, h->stream));
   }
   float *tag32 = nullptr;

@@ -39,6 +39,7 @@ struct DevState {
   int ir_inner_total; // batched solves: inner outer iterations over all refinements
   double ir_bb;       // ||b||^2 of the FP64 system
   double ir_rtol;     // outer (FP64) relative tolerance
+  double ir_inner_rtol; // inner solves: relative reduction of the inner residual
   double bb;          // ||b||^2
   double rr;          // ||r||^2 after the latest update
   double rtol;

@@ -216,6 +216,10 @@ struct EpiIrResidual {
     st->bb = rr32;
     st->rr = rr32;
     st->k = 0;
+    // the inner solve reduces its residual by ir_inner_rtol, but not below
+    // half of what the outer test still needs (no over-solving at the end)
+    const double need = 0.5 * st->ir_rtol * bn / sqrt(rr32);
+    st->rtol = need > st->ir_inner_rtol ? need : st->ir_inner_rtol;
     if (bb == 0.0) st->status = ST_ZERO_RHS;
     else if (rn <= st->ir_rtol * bn) st->status = ST_CONVERGED;
     else if (j >= st->ir_max_refine) st->status = ST_MAXIT;
@@ -228,6 +232,9 @@ struct EpiIrResidual {
 // Kernels
 // --------------------------------------------------------------------------
 
+// Partial sums are stored at the workgroup's logical index, i.e. in the
+// order of the row chunks, so any launch that splits rows into the same
+// chunks (the batched solver included) reduces them in the same order.
 template <class Epi>
 __device__ __forceinline__ void epi_tail(const double (&part)[Epi::NP > 0 ? Epi::NP : 1],
                                          double *partials) {
@@ -235,7 +242,7 @@ __device__ __forceinline__ void epi_tail(const double (&part)[Epi::NP > 0 ? Epi:
     double v[Epi::NP];
 #pragma unroll
     for (int c = 0; c < Epi::NP; ++c) v[c] = part[c];
-    block_store_sums<Epi::NP>(v, partials + blockIdx.x, gridDim.x);
+    block_store_sums<Epi::NP>(v, partials + logical_block(), gridDim.x);
   }
 }
 
@@ -369,7 +376,7 @@ __global__ __launch_bounds__(kWG) void k_update(int64_t n, int64_t ld, T *__rest
   int64_t lo, hi;
   block_chunk(n, logical_block(), gridDim.x, lo, hi);
   double v[1] = {update_rows<S, T>(c, lo, hi, ld, Pc, Po, x, r, pc)};
-  block_store_sums<1>(v, partials + blockIdx.x, gridDim.x);
+  block_store_sums<1>(v, partials + logical_block(), gridDim.x);
 }
 
 // After the block update: ||r||^2, history entry, stopping test, k += 1.
@@ -418,7 +425,7 @@ static __global__ __attribute__((unused)) __launch_bounds__(kWG) void k_pcg_upda
     rr += ri * ri;
   }
   double v[2] = {ur, rr};
-  block_store_sums<2>(v, partials + blockIdx.x, gridDim.x);
+  block_store_sums<2>(v, partials + logical_block(), gridDim.x);
 }
 
 // After the PCG update: beta = u_{k+1}^T r_{k+1} / u_k^T r_k, history entry,
