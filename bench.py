@@ -38,23 +38,24 @@ MAXIT = 20000
 
 def algorithmic_bytes(n, nnz):
     """Bytes one launch of each kernel class must move (FP64 values and
-    vectors, int32 indices), per the byte model of the design notes.
-      matrix power j < s: val + colind (12 nnz) + rowptr (4n) + x, AZ_j, Z_{j+1},
-                          dinv (32 n)
-      last power + moments: 12 nnz + 4 n + x, AZ_s, r (24 n) + Z(:,1..s-1) (8(s-1) n)
-      block update: Z, AZ, P_old, AP_old (32 s n) + x, r read and written (32 n)
-                    + z1 and dinv (16 n)
+    vectors, int32 indices; the 7-point matrix has a constant diagonal, so
+    the Jacobi scaling is one constant and reads no vector):
+      matrix power j < s: val + colind (12 nnz) + rowptr (4 n) + x, AZ_j, Z_{j+1} (24 n)
+      last power + moments: 12 nnz + 4 n + x, AZ_s, r (24 n) + Z(:,1..s-1) (8 (s-1) n)
+      block update: reads Z, AZ, P_old, AP_old, x, r (8 (4s + 2) n),
+                    writes P, AP, x, r, z1 (8 (2s + 3) n)
     """
     return {
-        "mpk": 12 * nnz + 4 * n + 32 * n,
+        "mpk": 12 * nnz + 4 * n + 24 * n,
         "mpk_last": 12 * nnz + 4 * n + 24 * n + 8 * (S - 1) * n,
-        "update": 32 * S * n + 32 * n + 16 * n,
+        "update": 8 * (4 * S + 2) * n + 8 * (2 * S + 3) * n,
     }
 
 
 def kernel_source_sha():
     h = hashlib.sha256()
-    for f in ("common.hpp", "kernels.hpp", "small_solve.hpp", "capi.hip"):
+    for f in ("common.hpp", "operators.hpp", "kernels.hpp", "small_solve.hpp", "engine.hpp",
+              "setup_kernels.hpp", "capi.hip"):
         with open(os.path.join(ROOT, "paper_2501_03743_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -102,6 +103,137 @@ def cpu_baseline(gpu_outer, budget_s=20.0):
                       "scaled to the %d outer iterations of the full solve" % (k2, S, per, gpu_outer)}
 
 
+def bench_batch(H, seed=0, log=None):
+    """32 variable-coefficient 7-point systems, sides L ~ U{32..160}, k =
+    exp(g) with g a Gaussian random field (sigma 0.5, correlation length 0.1),
+    b ~ N(0, 1): one persistent launch (autotuned tiles and schedule) against
+    the same systems solved one after another, all to rtol 1e-8 with FP32
+    matrix powers and FP64 moments, s x s solves and refinement."""
+    import torch
+    from paper_2501_03743_amd import sstep
+    from paper_2501_03743_amd import workloads as wl
+    sides = [int(v) for v in wl.batch_sides(seed)]
+    mats, bs, keep = [], [], []
+    for i, L in enumerate(sides):
+        shape = (L, L, L)
+        k = torch.exp(wl.gaussian_random_field_device(shape, 0.5, 0.1, 1000 + i))
+        mats.append(H.matrix_stencil("3d7_vark", shape, k=k))
+        bs.append(torch.from_numpy(wl.normal_rhs(L ** 3, 2000 + i)).cuda())
+        keep.append(k)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    tune = H.autotune_batch(mats, bs, s=S)
+    tune_s = time.perf_counter() - t
+    xs = [torch.zeros_like(b) for b in bs]
+
+    def batch_once():
+        for v in xs:
+            v.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, st, it, tr = H.solve_batch(mats, bs, xs, s=S, rtol=RTOL, maxit=MAXIT, tune=tune)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, st, it, tr
+
+    batch_once()
+    reps = [batch_once() for _ in range(3)]
+    t_batch = min(r[0] for r in reps)
+    _, st, it, tr = reps[-1]
+
+    def seq_once(precision):
+        res = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for M, b, v in zip(mats, bs, xs):
+            v.zero_()
+            res.append(H.solve(M, b, v, s=S, rtol=RTOL, maxit=MAXIT, precision=precision))
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, res
+
+    seq_once("mixed_ir")
+    t_seq, res_seq = min((seq_once("mixed_ir") for _ in range(2)), key=lambda r: r[0])
+    t_seq64, res64 = seq_once("fp64")
+    out = {
+        "workload": "32 x 3D 7-point variable-coefficient Poisson, L ~ U{32..160} (sum n = %d), "
+                    "k = exp(GRF sigma 0.5, l 0.1), b ~ N(0,1), s=4, rtol 1e-8" % sum(L ** 3 for L in sides),
+        "sides": sides,
+        "tune": tune.as_dict(), "autotune_s": tune_s,
+        "batch_one_launch_s": t_batch,
+        "sequential_mixed_s": t_seq,
+        "sequential_fp64_s": t_seq64,
+        "speedup_vs_sequential_mixed": t_seq / t_batch,
+        "all_converged": bool((st == 0).all()) and all(r.status == 0 for r in res_seq),
+        "max_true_rel_batch": float(np.max(tr)),
+        "max_true_rel_sequential": float(max(r.true_rel for r in res_seq)),
+    }
+    for M in mats:
+        M.close()
+    return out
+
+
+def bench_warmstart(H, n_train=2000, n_eval=200, side=96, epochs=12, lr=2e-3, batch=4,
+                    log=None):
+    """The learned warm start on -div(k grad u) = f at side^3: log k a Gaussian
+    random field (sigma 1, correlation length 0.1), f a random sum of 16
+    Fourier modes; the network trained on n_train solver solutions (seeds
+    10000..), evaluated on n_eval held-out seeds (20000..) against x0 = 0, and
+    the mixed-precision + warm-start form against plain FP64 s-step and
+    standard CG at the same tolerance."""
+    import torch
+    from paper_2501_03743_amd import warmstart as ws
+    from paper_2501_03743_amd import workloads as wl
+    shape = (side, side, side)
+    t0 = time.time()
+    data = ws.generate(H, shape, list(range(10000, 10000 + n_train)), s=S, rtol=RTOL, log=log)
+    gen_s = time.time() - t0
+    model = ws.WarmStart(H, shape, batch=batch, seed=0)
+    t0 = time.time()
+    hist = model.fit(data, epochs, lr=lr, log=log)
+    train_s = time.time() - t0
+    del data
+    torch.cuda.empty_cache()
+    seeds = list(range(20000, 20000 + n_eval))
+    rec = ws.evaluate(H, model, seeds, s=S, rtol=RTOL)
+    summ = ws.summarize(rec)
+    # the full forms at equal final accuracy on the first held-out seeds
+    forms = {}
+    m = min(20, n_eval)
+    for name, kw, warm in (("pcg_fp64_x0_0", {"method": "pcg"}, False),
+                           ("sstep_fp64_x0_0", {}, False),
+                           ("sstep_mixed_x0_0", {"precision": "mixed_ir"}, False),
+                           ("sstep_mixed_warm", {"precision": "mixed_ir"}, True)):
+        ts, its, trs = [], [], []
+        for seed in seeds[:m]:
+            logk, k, f, b = wl.warm_start_problem(shape, seed)
+            A = H.matrix_stencil("3d7_vark", shape, k=k)
+            x = torch.zeros_like(b)
+            if kw.get("precision"):
+                H.solve(A, b, x, s=S, rtol=RTOL, **kw)   # FP32 copy built outside the timing
+                x.zero_()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            if warm:
+                model.predict(logk, f, out=x)
+            r = H.solve(A, b, x, s=S, rtol=RTOL, maxit=MAXIT, warm_start=warm, **kw)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t1)
+            its.append(r.cg_equiv if kw.get("method") != "pcg" else r.outer)
+            trs.append(r.true_rel)
+            A.close()
+        forms[name] = {"mean_s": float(np.mean(ts)), "mean_cg_steps": float(np.mean(its)),
+                       "max_true_rel": float(np.max(trs))}
+    params = model.net.count
+    model.close()
+    return {
+        "workload": "-div(k grad u)=f on %d^3, log k GRF (sigma 1, l 0.1), f = 16 Fourier modes, "
+                    "s=4, rtol 1e-8" % side,
+        "train_samples": n_train, "eval_samples": n_eval, "epochs": len(hist),
+        "generate_s": gen_s, "train_s": train_s, "loss_first": hist[0], "loss_last": hist[-1],
+        "params": params,
+        "held_out": summ, "forms_first_%d" % m: forms,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +244,14 @@ def main():
                     help="skip the 256^3 27-point FP64 / mixed-precision comparison")
     ap.add_argument("--only-timed", action="store_true",
                     help="only the timed solves (for profiler runs)")
+    ap.add_argument("--batch", action="store_true",
+                    help="add the batched-solve comparison (32 uneven variable-coefficient systems)")
+    ap.add_argument("--warmstart", action="store_true",
+                    help="only the learned warm start (trains the network; several minutes)")
+    ap.add_argument("--ws-train", type=int, default=2000)
+    ap.add_argument("--ws-eval", type=int, default=200)
+    ap.add_argument("--ws-side", type=int, default=96)
+    ap.add_argument("--ws-epochs", type=int, default=12)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only a plain 1 GiB device-to-device copy, three times (the "
                          "reference for the FETCH_SIZE / WRITE_SIZE counter scale)")
@@ -135,6 +275,12 @@ def main():
         print(json.dumps({"copy_bytes": src.numel() * 8, "copies": 3}))
         return
     H = sstep.Handle(0)
+    if args.warmstart:
+        def log(m):
+            print("[warmstart] " + m, file=sys.stderr, flush=True)
+        print(json.dumps({"config_warm_start": bench_warmstart(
+            H, args.ws_train, args.ws_eval, args.ws_side, args.ws_epochs, log=log)}))
+        return
     n = N ** 3
     A = H.matrix_csr_from_stencil("3d7", (N, N, N))
     b = torch.from_numpy(wl.normal_rhs(n, SEED)).cuda()
@@ -263,6 +409,8 @@ def main():
         A2.close()
         del b2, x2, xref
 
+    config3 = bench_batch(H) if args.batch else None
+
     out = {
         "metric": "time-to-solution @rtol 1e-8 (s) + SpMV/matrix-powers HBM GB/s, s-step vs CG",
         "value": tts,
@@ -302,6 +450,7 @@ def main():
             "spmv": spmv,
         },
         "config_27pt_256_mixed": config2,
+        "config_batch32": config3,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(res.outer)

@@ -99,6 +99,10 @@ typedef struct ssp_opts {
   double *trace_alpha; /* host, trace_cap * s                                   */
   double *trace_beta;  /* host, trace_cap * s * s                               */
   double *trace_W;     /* host, trace_cap * s * s                               */
+  int warm_start;      /* 1: x holds a predicted initial guess (e.g. the warm-
+                          start network's); it is judged by its true residual
+                          before the solve and replaced by x = 0 when
+                          ||b - A x|| >= ||b|| (see ssp_get_warm_start)         */
 } ssp_opts;
 
 /* ---- handle ---------------------------------------------------------------- */
@@ -181,6 +185,11 @@ int ssp_solve(ssp_handle *h, const ssp_matrix *A, const double *b, double *x, in
 /* Outer iterations and CG-equivalent steps (s * outer) of the last solve. */
 int ssp_get_iterations(const ssp_handle *h, int *outer, int *cg_equiv);
 
+/* Outcome of the last solve's warm-start judge (opts.warm_start = 1):
+ * *kept = 1 if the given x was used, 0 if it fell back to x = 0, -1 if the
+ * last solve had no warm start; *rel0 = ||b - A x_given|| / ||b||. */
+int ssp_get_warm_start(const ssp_handle *h, int *kept, double *rel0);
+
 /* ||r_i||_2/||b||_2 of the last solve, i = 0 (initial) .. outer; copies at most
  * cap entries into the HOST buffer and sets *len to the full length. */
 int ssp_get_residual_history(const ssp_handle *h, double *buf, int cap, int *len);
@@ -237,6 +246,71 @@ int ssp_solve_batch(ssp_handle *h, int nsys, const ssp_matrix *const *A,
 int ssp_autotune_batch(ssp_handle *h, int nsys, const ssp_matrix *const *A,
                        const double *const *b, int s, const char *cache_path,
                        ssp_tune *out);
+
+/* ---- learned warm start --------------------------------------------------- */
+
+/* A 3-level U-shaped 3D conv net (about 246k parameters) that maps the pair
+ * (log k, f) of a variable-coefficient Poisson problem on a D x H x W grid
+ * to an initial guess x0 (the learned-warm-start extension).  Convolutions
+ * run on the BF16 matrix cores with FP32 accumulation; master weights, Adam
+ * moments and gradients are FP32.  Layers: 3x3x3 convolutions
+ * 8->16, 16->16, 16->32 (stride 2), 32->32, 32->48 (stride 2), 48->48,
+ * 80->32 (after nearest upsampling and concatenation with the 32-channel
+ * level), 48->16 (likewise with the 16-channel level), then a 1x1 head
+ * 16->1; ReLU after every 3x3x3 convolution; zero padding of one cell.
+ * Weights are He-normal from `seed`, biases zero. */
+typedef struct ssp_net ssp_net;
+
+int ssp_net_create(ssp_handle *h, int D, int H, int W, int max_batch, uint64_t seed,
+                   ssp_net **net);
+int ssp_net_destroy(ssp_net *net);
+
+/* DEVICE pointers to the flat FP32 parameters and gradients (layout: per
+ * layer W[27][Ci][Co] then b[Co], then the head's w[16] and b[1]) and their
+ * count. */
+int ssp_net_params(ssp_net *net, float **params, float **grads, int64_t *count);
+
+/* Forward pass.  in: DEVICE FP32 [batch][D][H][W][2] (log k and f, already
+ * normalised), out: DEVICE FP32 [batch][D][H][W].  Keeps the activations for
+ * ssp_net_backward. */
+int ssp_net_forward(ssp_net *net, const float *in, int batch, float *out);
+
+/* Squared-error loss of the last forward's output y against target (DEVICE
+ * FP32, batch*D*H*W): writes dy = 2 (y - t) / N (DEVICE) and, if loss is a
+ * HOST pointer, the mean squared error (synchronises). */
+int ssp_net_loss(ssp_net *net, const float *y, const float *target, float *dy, double *loss);
+
+/* Accumulates the parameter gradients of the last forward for the output
+ * gradient dy (DEVICE FP32); ssp_net_zero_grad clears them. */
+int ssp_net_backward(ssp_net *net, const float *dy);
+int ssp_net_zero_grad(ssp_net *net);
+
+/* One Adam step with bias correction (step counts from 1). */
+int ssp_net_adam_step(ssp_net *net, float lr, float beta1, float beta2, float eps, int step);
+
+/* Checkpoint: parameters, then Adam first and second moments (3 * count
+ * floats, HOST buffer).  set_state accepts count (parameters only) or
+ * 3 * count floats. */
+int ssp_net_get_state(ssp_net *net, float *host, int64_t cap);
+int ssp_net_set_state(ssp_net *net, const float *host, int64_t len);
+
+/* One 3x3x3 convolution (zero padding 1, stride 1 or 2) on its own, with the
+ * network's kernels; inputs are rounded to BF16, results are FP32.  mode 0:
+ * out = conv(in, w) for in [B][D][H][W][ci] (ci % 8 == 0, co % 16 == 0);
+ * mode 1: out = the input gradient for the output gradient `in`
+ * ([B][Do][Ho][Wo][co]; ci % 16 == 0, co % 8 == 0).  w: FP32 [27][ci][co]
+ * with tap (dz+1)*9 + (dy+1)*3 + (dx+1).  DEVICE pointers; synchronises. */
+int ssp_conv3d(ssp_handle *h, int mode, const float *in, int B, int D, int H, int W, int ci,
+               const float *w, int co, int stride, float *out);
+
+/* Weight and bias gradients of that convolution for input x and output
+ * gradient dz (DEVICE, FP32, rounded to BF16): dw [27][ci][co], db [co]. */
+int ssp_conv3d_wgrad(ssp_handle *h, const float *x, int B, int D, int H, int W, int ci,
+                     const float *dz, int co, int stride, float *dw, float *db);
+
+/* One 16x16x32 BF16 matrix-core product D = A B with the operand layout the
+ * convolutions use (DEVICE FP32 row-major A 16x32, B 32x16, D 16x16). */
+int ssp_net_mfma_selftest(ssp_handle *h, const float *A, const float *B, float *D);
 
 /* Text for a status code (static storage). */
 const char *ssp_status_string(int status);

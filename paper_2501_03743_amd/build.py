@@ -16,7 +16,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libsstep.so")
-SOURCES = ["capi.hip", "inst_f64.hip", "inst_f32.hip", "batch.hip"]
+SOURCES = ["capi.hip", "inst_f64.hip", "inst_f32.hip", "batch.hip", "unet.hip"]
 HEADERS = ["common.hpp", "operators.hpp", "small_solve.hpp", "kernels.hpp",
            "setup_kernels.hpp", "engine.hpp", "batch.hpp"]
 

@@ -220,8 +220,10 @@ int csr_pick_variant(ssp_handle *h, ssp_matrix *A) {
   h->prof_on = false;
   int rc = ensure_workspace(h, 1, 1, 1, false);
   if (rc) return rc;
-  double *y = nullptr;
+  double *y = nullptr, *xv = nullptr;
   HIPCHK(h, hipMalloc(&y, sizeof(double) * A->n));
+  HIPCHK(h, hipMalloc(&xv, sizeof(double) * A->n));
+  HIPCHK(h, hipMemsetAsync(xv, 0, sizeof(double) * A->n, h->stream));
   hipEvent_t e0, e1;
   HIPCHK(h, hipEventCreate(&e0));
   HIPCHK(h, hipEventCreate(&e1));
@@ -229,11 +231,11 @@ int csr_pick_variant(ssp_handle *h, ssp_matrix *A) {
   int best_v = CSR_STAGED;
   for (int v = CSR_STAGED; v <= CSR_ROW && rc == SSP_OK; ++v) {
     A->csr.variant = v;
-    rc = launch_op<double>(h, A, A->dinv, EpiStore<double>{y}, 0);  // warm-up
+    rc = launch_op<double>(h, A, xv, EpiStore<double>{y}, 0);  // warm-up
     if (rc) break;
     (void)hipEventRecord(e0, h->stream);
     for (int t = 0; t < 3 && rc == SSP_OK; ++t)
-      rc = launch_op<double>(h, A, A->dinv, EpiStore<double>{y}, 0);
+      rc = launch_op<double>(h, A, xv, EpiStore<double>{y}, 0);
     (void)hipEventRecord(e1, h->stream);
     (void)hipEventSynchronize(e1);
     float ms = 0.f;
@@ -247,6 +249,7 @@ int csr_pick_variant(ssp_handle *h, ssp_matrix *A) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipFree(y);
+  (void)hipFree(xv);
   return rc;
 }
 
@@ -271,6 +274,23 @@ int csr_finish_setup(ssp_handle *h, ssp_matrix *A) {
   k_csr_dinv<<<(unsigned)nb, kWG, 0, h->stream>>>(A->n, A->csr.rowptr, A->csr.colind,
                                                   A->csr.val, A->dinv);
   LAUNCHCHK(h);
+  // a constant diagonal needs no Jacobi vector (same values, less traffic)
+  int *d_diff = nullptr;
+  HIPCHK(h, hipMalloc(&d_diff, sizeof(int)));
+  HIPCHK(h, hipMemsetAsync(d_diff, 0, sizeof(int), h->stream));
+  k_all_equal<<<(unsigned)nb, kWG, 0, h->stream>>>(A->n, A->dinv, d_diff);
+  LAUNCHCHK(h);
+  int differs = 1;
+  double d0 = 0.0;
+  HIPCHK(h, hipMemcpyAsync(&differs, d_diff, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipMemcpyAsync(&d0, A->dinv, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  (void)hipFree(d_diff);
+  if (!differs && std::isfinite(d0) && d0 > 0.0) {
+    A->dconst = d0;
+    (void)hipFree(A->dinv);
+    A->dinv = nullptr;
+  }
   return csr_pick_variant(h, A);
 }
 
@@ -309,6 +329,23 @@ int stencil_args(ssp_handle *h, int kind, int nx, int ny, int nz, const double *
 // ---------------------------------------------------------------------------
 // solves
 // ---------------------------------------------------------------------------
+
+// The true-residual judge of a predicted initial guess: x is kept only if
+// ||b - A x|| < ||b|| (a non-finite residual also falls back), else x = 0.
+int warm_start_judge(ssp_handle *h, const ssp_matrix *A, const double *b, double *x) {
+  Workspace &w = h->ws;
+  if (!w.partials) HIPCHK(h, hipMalloc(&w.partials, sizeof(double) * kGridMax * 2 * kSMax));
+  int rc = launch_op<double>(h, A, x, EpiWarmCheck{b}, 3);
+  if (rc) return rc;
+  rc = read_state(h, false);
+  if (rc) return rc;
+  const double bb = h->h_read->bb, rr = h->h_read->true_rr;
+  h->last_warm_rel0 = bb > 0.0 ? std::sqrt(rr / bb) : 0.0;
+  const bool keep = bb > 0.0 && rr < bb;
+  h->last_warm_kept = keep ? 1 : 0;
+  if (!keep) HIPCHK(h, hipMemsetAsync(x, 0, sizeof(double) * A->n, h->stream));
+  return SSP_OK;
+}
 
 int solve_sstep(ssp_handle *h, const ssp_matrix *A, const double *b, double *x, int s,
                 double rtol, int maxit, const ssp_opts *o) {
@@ -823,6 +860,12 @@ int ssp_solve(ssp_handle *h, const ssp_matrix *A, const double *b, double *x, in
     h->prof_launch[c] = 0;
     h->prof_ms[c] = 0.0;
   }
+  h->last_warm_kept = -1;
+  h->last_warm_rel0 = NAN;
+  if (opts && opts->warm_start) {
+    rc = warm_start_judge(h, A, b, x);
+    if (rc) return rc;
+  }
   if (precision == SSP_PRECISION_MIXED_IR)
     return solve_mixed(h, const_cast<ssp_matrix *>(A), b, x, s, rtol, maxit, opts);
   if (method == SSP_METHOD_PCG) return solve_pcg(h, A, b, x, rtol, maxit, opts);
@@ -833,6 +876,13 @@ int ssp_get_iterations(const ssp_handle *h, int *outer, int *cg_equiv) {
   if (!h) return SSP_EINVAL;
   if (outer) *outer = h->last_outer;
   if (cg_equiv) *cg_equiv = h->last_outer * h->last_s;
+  return SSP_OK;
+}
+
+int ssp_get_warm_start(const ssp_handle *h, int *kept, double *rel0) {
+  if (!h) return SSP_EINVAL;
+  if (kept) *kept = h->last_warm_kept;
+  if (rel0) *rel0 = h->last_warm_rel0;
   return SSP_OK;
 }
 

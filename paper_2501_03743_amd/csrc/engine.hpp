@@ -48,6 +48,8 @@ struct ssp_handle {
   int last_outer = 0, last_s = 1;
   double last_true_rel = NAN;
   std::vector<double> last_hist;
+  int last_warm_kept = -1;         // warm-start judge: 1 kept, 0 fell back, -1 none
+  double last_warm_rel0 = NAN;
   // profiling (HIP events around launches)
   bool prof_on = false;
   std::vector<hipEvent_t> ev;
@@ -181,7 +183,12 @@ int launch_op(ssp_handle *h, const ssp_matrix *A, const T *x, const Epi &epi, in
   prof_begin(h, cls);
   switch (A->kind) {
     case 0:
-      k_csr<T, Epi><<<G, kWG, 0, h->stream>>>(csr_of(A, tag), x, epi, h->st, h->ws.partials);
+      if (A->csr.variant == CSR_ROW)
+        k_csr<CSR_ROW, T, Epi><<<G, kWG, 0, h->stream>>>(csr_of(A, tag), x, epi, h->st,
+                                                          h->ws.partials);
+      else
+        k_csr<CSR_STAGED, T, Epi><<<G, kWG, 0, h->stream>>>(csr_of(A, tag), x, epi, h->st,
+                                                             h->ws.partials);
       break;
     case SSP_STENCIL_2D5:
       k_stencil<K_2D5, T, Epi><<<G, kWG, 0, h->stream>>>(sten_of(A, tag), x, epi, h->st,

@@ -82,6 +82,41 @@ struct EpiMpkLast {
   }
 };
 
+// Epilogue data that can be loaded before the row's product is formed.  By
+// default there is none; the last matrix power prefetches Z(i,1..s) and r(i).
+template <class Epi>
+__device__ __forceinline__ NoPre epi_pre(const Epi &, int64_t) {
+  return NoPre{};
+}
+template <class Epi, typename T>
+__device__ __forceinline__ void epi_row(const Epi &e, int64_t i, T v, const NoPre &, double *part) {
+  e.row(i, v, part);
+}
+template <int S>
+struct LastPre {
+  double z[S];
+  double r;
+};
+template <int S, typename T>
+__device__ __forceinline__ LastPre<S> epi_pre(const EpiMpkLast<S, T> &e, int64_t i) {
+  LastPre<S> p;
+#pragma unroll
+  for (int a = 0; a < S; ++a) p.z[a] = (double)e.Z[(int64_t)a * e.ld + i];
+  p.r = (double)e.r[i];
+  return p;
+}
+template <int S, typename T>
+__device__ __forceinline__ void epi_row(const EpiMpkLast<S, T> &e, int64_t i, T v,
+                                        const LastPre<S> &p, double *part) {
+  e.az[i] = v;
+  const double vi = (double)v;
+#pragma unroll
+  for (int a = 0; a < S; ++a) {
+    part[a] += p.z[a] * p.r;
+    part[S + a] += p.z[a] * vi;
+  }
+}
+
 // Sets the status after the residual norms of a starting iterate are known.
 __device__ __forceinline__ void start_status(DevState *st, double bb, double rr, double *hist) {
   st->bb = bb;
@@ -180,6 +215,27 @@ struct EpiTrueRes {
   }
 };
 
+// Judge of a warm start x0: ||b||^2 and ||b - A x0||^2 (runs whatever the
+// status; the host compares them before the solve starts).
+struct EpiWarmCheck {
+  static constexpr int NP = 2;
+  static constexpr bool kCheck = false;
+  const double *b;
+  __device__ __forceinline__ void row(int64_t i, double v, double *part) const {
+#pragma clang fp contract(off)
+    const double bi = b[i];
+    const double t = bi - v;
+    part[0] += bi * bi;
+    part[1] += t * t;
+  }
+  __device__ __forceinline__ void finish(DevState *st, const double *tot) const {
+    if (threadIdx.x == 0) {
+      st->bb = tot[0];
+      st->true_rr = tot[1];
+    }
+  }
+};
+
 // Iterative refinement, outer step: the FP64 residual r = b - A x of the
 // current FP64 iterate, rounded to FP32 as the right-hand side of the next
 // inner solve; the inner iterate d starts at 0, so the inner residual is that
@@ -257,14 +313,16 @@ __global__ __launch_bounds__(kWG) void k_finalize(Fin fin, DevState *st, const d
   fin.finish(st, tot);
 }
 
-template <typename T, class Epi>
+template <int VARIANT, typename T, class Epi>
 __global__ __launch_bounds__(kWG) void k_csr(CsrArgs<T> A, const T *__restrict__ x, Epi epi,
                                              DevState *st, double *partials) {
   if (Epi::kCheck && st->status != ST_RUNNING) return;
   double part[Epi::NP > 0 ? Epi::NP : 1];
 #pragma unroll
   for (int c = 0; c < (Epi::NP > 0 ? Epi::NP : 1); ++c) part[c] = 0.0;
-  csr_rows(A, x, [&](int64_t i, T v) { epi.row(i, v, part); });
+  csr_rows<VARIANT>(
+      A, x, [&](int64_t i) { return epi_pre(epi, i); },
+      [&](int64_t i, T v, const auto &p) { epi_row(epi, i, v, p, part); });
   epi_tail<Epi>(part, partials);
 }
 

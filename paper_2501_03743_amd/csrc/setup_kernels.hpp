@@ -103,6 +103,14 @@ __global__ __launch_bounds__(kWG) void k_stencil_fill(StencilArgs<double> S, con
   }
 }
 
+// Sets *differs if some dinv[i] is not bitwise equal to dinv[0].
+__global__ __launch_bounds__(kWG) void k_all_equal(int64_t n, const double *__restrict__ v,
+                                                   int *differs) {
+  const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (i >= n) return;
+  if (__double_as_longlong(v[i]) != __double_as_longlong(v[0])) atomicOr(differs, 1);
+}
+
 // Longest row of a CSR matrix (one atomicMax per workgroup).
 __global__ __launch_bounds__(kWG) void k_csr_maxrow(int64_t n, const int32_t *rowptr,
                                                     int *out) {

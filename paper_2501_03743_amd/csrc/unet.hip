@@ -1,0 +1,870 @@
+// The warm-start network: a 3-level U-shaped 3D conv net that maps the
+// coefficient field and source of a variable-coefficient Poisson problem to
+// an initial guess x0 for the s-step solver (the learned-warm-start
+// extension).  Training and inference run in these kernels:
+//
+//   * 3x3x3 convolutions (stride 1 or 2, zero padding 1) as implicit GEMMs on
+//     the BF16 matrix cores (v_mfma_f32_16x16x32_bf16), FP32 accumulation;
+//     the input gradient is the same kernel run on the transposed problem;
+//   * weight gradients as FP32 tile reductions (fixed order, deterministic);
+//   * nearest-neighbour upsampling, channel concatenation, ReLU masks, a 1x1
+//     head, the squared-error loss and Adam, as streaming kernels.
+//
+// Tensors are channels-last [B, D, H, W, C]; activations are BF16, gradients
+// FP32, master weights and Adam moments FP32.  Layer table (Ci -> Co, stride):
+//   e1a 8->16, e1b 16->16, d1 16->32 /2, e2 32->32, d2 32->48 /2, bott 48->48,
+//   u2 80->32 (up(bott) ++ e2), u1 48->16 (up(u2) ++ e1b), head 16->1.
+#include <cstdint>
+#include <cstring>
+#include <random>
+#include <vector>
+
+#include "engine.hpp"
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+using namespace ssp;
+
+constexpr int kLayers = 8;
+constexpr int kHeadC = 16;
+struct LayerDef {
+  int ci, co, stride;
+};
+constexpr LayerDef kDef[kLayers] = {{8, 16, 1},  {16, 16, 1}, {16, 32, 2}, {32, 32, 1},
+                                    {32, 48, 2}, {48, 48, 1}, {80, 32, 1}, {48, 16, 1}};
+enum { L_E1A, L_E1B, L_D1, L_E2, L_D2, L_BOTT, L_U2, L_U1 };
+
+struct Grid3 {
+  int B, D, H, W;
+  __host__ __device__ int64_t points() const { return (int64_t)B * D * H * W; }
+};
+
+__device__ __forceinline__ void decode(int64_t p, const Grid3 &g, int &b, int &z, int &y,
+                                       int &x) {
+  x = (int)(p % g.W);
+  int64_t t = p / g.W;
+  y = (int)(t % g.H);
+  t /= g.H;
+  z = (int)(t % g.D);
+  b = (int)(t / g.D);
+}
+
+__device__ __forceinline__ int64_t encode(int b, int z, int y, int x, const Grid3 &g) {
+  return (((int64_t)b * g.D + z) * g.H + y) * g.W + x;
+}
+
+// --------------------------------------------------------------------------
+// Convolution as an implicit GEMM on the matrix cores
+// --------------------------------------------------------------------------
+//
+// out[p, n] = sum_k A[p, k] Wt[n, k] with k = tap * Cin + c over the 27 taps
+// (tap = (dz+1)*9 + (dy+1)*3 + (dx+1)) and Cin input channels, padded to a
+// multiple of 32.  Each wavefront owns 16 output points and all NS*16 output
+// channels; one v_mfma_f32_16x16x32_bf16 per 32-wide k chunk and 16 channels.
+// Operand layout of the instruction (per lane l, m = l % 16, g = l / 16):
+//   A: row m, k = 8g .. 8g+7        B: column m, k = 8g .. 8g+7
+//   D: rows 4g .. 4g+3, column m
+// MODE 0 (forward):  input point q = stride * p + (dz, dy, dx)
+// MODE 1 (input gradient of a stride-s convolution): q = (p - (dz, dy, dx)) / s
+//   when divisible; here "in" is the output gradient and Wt holds W
+//   transposed to [Ci][tap * Co + co].
+template <int MODE, int NS>
+__global__ __launch_bounds__(256) void k_conv_mfma(const bf16 *__restrict__ in, int cin, Grid3 gi,
+                                                   Grid3 go, int stride,
+                                                   const bf16 *__restrict__ wt, int kp,
+                                                   const float *__restrict__ bias, int relu,
+                                                   float *__restrict__ out_f, bf16 *__restrict__ out_b) {
+  __shared__ int s_tap[512];      // k/8 -> tap
+  __shared__ int s_ci[512];       // k/8 -> channel offset
+  const int nk8 = kp / 8;
+  for (int i = threadIdx.x; i < nk8; i += 256) {
+    const int k = i * 8;
+    const int t = k / cin;
+    s_tap[i] = t;
+    s_ci[i] = k - t * cin;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  const int m = lane % 16, g = lane / 16;
+  const int64_t P = go.points();
+  const int64_t p = (int64_t)blockIdx.x * 64 + wave * 16 + m;
+  const bool valid = p < P;
+  int b = 0, z = 0, y = 0, x = 0;
+  if (valid) decode(p, go, b, z, y, x);
+  f32x4 acc[NS];
+#pragma unroll
+  for (int n = 0; n < NS; ++n) acc[n] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const bf16x8 zero8 = {};
+  for (int kc = 0; kc < kp; kc += 32) {
+    const int i8 = (kc >> 3) + g;
+    const int t = s_tap[i8];
+    bf16x8 a = zero8;
+    if (valid && t < 27) {
+      const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+      int qz, qy, qx;
+      bool ok;
+      if (MODE == 0) {
+        qz = stride * z + dz;
+        qy = stride * y + dy;
+        qx = stride * x + dx;
+        ok = true;
+      } else {
+        qz = z - dz;
+        qy = y - dy;
+        qx = x - dx;
+        ok = true;
+        if (stride == 2) {
+          ok = ((qz | qy | qx) & 1) == 0;
+          qz >>= 1;
+          qy >>= 1;
+          qx >>= 1;
+        }
+      }
+      ok = ok && qz >= 0 && qz < gi.D && qy >= 0 && qy < gi.H && qx >= 0 && qx < gi.W;
+      if (ok) {
+        const int64_t q = encode(b, qz, qy, qx, gi);
+        a = *(const bf16x8 *)(in + q * cin + s_ci[i8]);
+      }
+    }
+#pragma unroll
+    for (int n = 0; n < NS; ++n) {
+      const bf16x8 w = *(const bf16x8 *)(wt + (int64_t)(n * 16 + m) * kp + kc + g * 8);
+      acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w, acc[n], 0, 0, 0);
+    }
+  }
+  const int cout = NS * 16;
+#pragma unroll
+  for (int n = 0; n < NS; ++n) {
+    const int c = n * 16 + m;
+    const float bs = bias ? bias[c] : 0.0f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t po = (int64_t)blockIdx.x * 64 + wave * 16 + 4 * g + i;
+      if (po < P) {
+        float v = acc[n][i] + bs;
+        if (relu) v = v > 0.0f ? v : 0.0f;
+        if (out_f) out_f[po * cout + c] = v;
+        if (out_b) out_b[po * cout + c] = (bf16)v;
+      }
+    }
+  }
+}
+
+// Weight gradient of one tap block: part[blk][t][ci][co] = sum over the
+// block's output points of x[q(p, t), ci] * dz[p, co] (FP32, fixed order).
+// Each thread owns a 4 x 4 (ci, co) register block.
+__global__ __launch_bounds__(256) void k_conv_wgrad(const bf16 *__restrict__ xin, int ci_n,
+                                                    Grid3 gi, Grid3 go, int stride,
+                                                    const bf16 *__restrict__ dz, int co_n,
+                                                    int64_t pts_per_blk, float *__restrict__ part,
+                                                    float *__restrict__ bpart) {
+  constexpr int TP = 32;  // points staged per step
+  __shared__ float sx[TP][80 + 1];
+  __shared__ float sd[TP][48 + 1];
+  const int t = blockIdx.y;
+  const int dz_ = t / 9 - 1, dy_ = (t / 3) % 3 - 1, dx_ = t % 3 - 1;
+  const int nci4 = ci_n / 4, nco4 = co_n / 4;
+  const int my = threadIdx.x;
+  const bool active = my < nci4 * nco4;
+  const int ci0 = active ? (my / nco4) * 4 : 0, co0 = active ? (my % nco4) * 4 : 0;
+  float acc[4][4] = {};
+  float bacc = 0.0f;   // tap-0 blocks: bias gradient of channel threadIdx.x
+  const int64_t P = go.points();
+  const int64_t p0 = (int64_t)blockIdx.x * pts_per_blk;
+  const int64_t p1 = p0 + pts_per_blk < P ? p0 + pts_per_blk : P;
+  for (int64_t pb = p0; pb < p1; pb += TP) {
+    for (int e = threadIdx.x; e < TP * ci_n; e += 256) {
+      const int j = e / ci_n, c = e - j * ci_n;
+      const int64_t p = pb + j;
+      float v = 0.0f;
+      if (p < p1) {
+        int b, z, y, x;
+        decode(p, go, b, z, y, x);
+        const int qz = stride * z + dz_, qy = stride * y + dy_, qx = stride * x + dx_;
+        if (qz >= 0 && qz < gi.D && qy >= 0 && qy < gi.H && qx >= 0 && qx < gi.W)
+          v = (float)xin[encode(b, qz, qy, qx, gi) * ci_n + c];
+      }
+      sx[j][c] = v;
+    }
+    for (int e = threadIdx.x; e < TP * co_n; e += 256) {
+      const int j = e / co_n, c = e - j * co_n;
+      const int64_t p = pb + j;
+      sd[j][c] = (p < p1) ? (float)dz[p * co_n + c] : 0.0f;
+    }
+    __syncthreads();
+    if (t == 0 && threadIdx.x < co_n)
+      for (int j = 0; j < TP; ++j) bacc += sd[j][threadIdx.x];
+    if (active) {
+      for (int j = 0; j < TP; ++j) {
+        float xv[4], dv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          xv[u] = sx[j][ci0 + u];
+          dv[u] = sd[j][co0 + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[u][v] += xv[u] * dv[v];
+      }
+    }
+    __syncthreads();
+  }
+  if (t == 0 && threadIdx.x < co_n) bpart[(int64_t)blockIdx.x * co_n + threadIdx.x] = bacc;
+  if (active) {
+    float *o = part + ((int64_t)blockIdx.x * 27 + t) * ci_n * co_n;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) o[(ci0 + u) * co_n + co0 + v] = acc[u][v];
+  }
+}
+
+// grad[i] += sum over blocks of part[blk][i] (fixed order).
+__global__ __launch_bounds__(256) void k_sum_blocks(const float *__restrict__ part, int nblk,
+                                                    int64_t m, float *__restrict__ grad) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= m) return;
+  float s = 0.0f;
+  for (int k = 0; k < nblk; ++k) s += part[(int64_t)k * m + i];
+  grad[i] += s;
+}
+
+// Packs FP32 weights W[27][Ci][Co] into BF16 GEMM operands:
+//   fwd: wf[co][t*Ci + ci]   (k padded to kpf with zeros)
+//   bwd: wb[ci][t*Co + co]   (k padded to kpb with zeros)
+__global__ __launch_bounds__(256) void k_pack(const float *__restrict__ w, int ci_n, int co_n,
+                                              bf16 *__restrict__ wf, int kpf,
+                                              bf16 *__restrict__ wb, int kpb) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t nf = (int64_t)co_n * kpf, nb = (int64_t)ci_n * kpb;
+  if (i < nf) {
+    const int co = (int)(i / kpf), k = (int)(i % kpf);
+    float v = 0.0f;
+    if (k < 27 * ci_n) {
+      const int t = k / ci_n, ci = k % ci_n;
+      v = w[((int64_t)t * ci_n + ci) * co_n + co];
+    }
+    wf[i] = (bf16)v;
+  }
+  if (wb && i < nb) {
+    const int ci = (int)(i / kpb), k = (int)(i % kpb);
+    float v = 0.0f;
+    if (k < 27 * co_n) {
+      const int t = k / co_n, co = k % co_n;
+      v = w[((int64_t)t * ci_n + ci) * co_n + co];
+    }
+    wb[i] = (bf16)v;
+  }
+}
+
+// --------------------------------------------------------------------------
+// Streaming kernels
+// --------------------------------------------------------------------------
+
+// x0[p, 0..7] = (in[p, 0], in[p, 1], 0, ...) in BF16.
+__global__ __launch_bounds__(256) void k_input(const float *__restrict__ in, int64_t P,
+                                               bf16 *__restrict__ x0) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= P) return;
+  for (int c = 0; c < 8; ++c) x0[p * 8 + c] = (bf16)(c < 2 ? in[p * 2 + c] : 0.0f);
+}
+
+// Concatenation buffer: buf[p, 0:cu] = up2(coarse)[p], buf[p, cu:cu+cs] = skip[p].
+__global__ __launch_bounds__(256) void k_up_concat(const bf16 *__restrict__ coarse, Grid3 gc,
+                                                   int cu, const bf16 *__restrict__ skip, int cs,
+                                                   Grid3 gf, bf16 *__restrict__ buf) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= gf.points()) return;
+  int b, z, y, x;
+  decode(p, gf, b, z, y, x);
+  const int64_t q = encode(b, z / 2, y / 2, x / 2, gc);
+  const int ct = cu + cs;
+  for (int c = 0; c < cu; ++c) buf[p * ct + c] = coarse[q * cu + c];
+  for (int c = 0; c < cs; ++c) buf[p * ct + cu + c] = skip[p * cs + c];
+}
+
+// Upsampling backward: g_coarse[q, c] = sum over the fine children of
+// g_fine[p, off + c] (fine tensor has ct channels).
+__global__ __launch_bounds__(256) void k_up_backward(const float *__restrict__ gfine, Grid3 gf,
+                                                     int ct, int off, int c_n, Grid3 gc,
+                                                     float *__restrict__ gcoarse) {
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= gc.points()) return;
+  int b, z, y, x;
+  decode(q, gc, b, z, y, x);
+  for (int c = 0; c < c_n; ++c) {
+    float s = 0.0f;
+    for (int oz = 0; oz < 2; ++oz)
+      for (int oy = 0; oy < 2; ++oy)
+        for (int ox = 0; ox < 2; ++ox) {
+          const int fz = 2 * z + oz, fy = 2 * y + oy, fx = 2 * x + ox;
+          if (fz < gf.D && fy < gf.H && fx < gf.W) s += gfine[encode(b, fz, fy, fx, gf) * ct + off + c];
+        }
+    gcoarse[q * c_n + c] = s;
+  }
+}
+
+// dz = BF16((g1[:, off1:] + g2[:, off2:]) * (act > 0)) over c_n channels.
+__global__ __launch_bounds__(256) void k_relu_grad(int64_t P, int c_n, const float *__restrict__ g1,
+                                                   int ct1, int off1, const float *__restrict__ g2,
+                                                   int ct2, int off2, const bf16 *__restrict__ act,
+                                                   bf16 *__restrict__ dz) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= P * c_n) return;
+  const int64_t p = i / c_n;
+  const int c = (int)(i - p * c_n);
+  float g = g1[p * ct1 + off1 + c];
+  if (g2) g += g2[p * ct2 + off2 + c];
+  dz[i] = (bf16)((float)act[i] > 0.0f ? g : 0.0f);
+}
+
+// dst[p, 0:c_n] = src[p, off:off+c_n] (src has ct channels).
+__global__ __launch_bounds__(256) void k_slice(const float *__restrict__ src, int ct, int off,
+                                               int c_n, int64_t P, float *__restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= P * c_n) return;
+  const int64_t p = i / c_n;
+  dst[i] = src[p * ct + off + (i - p * c_n)];
+}
+
+// 1x1 head: y[p] = sum_c a[p, c] w[c] + b.
+__global__ __launch_bounds__(256) void k_head(const bf16 *__restrict__ a, int64_t P,
+                                              const float *__restrict__ w, const float *__restrict__ b,
+                                              float *__restrict__ y) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= P) return;
+  float s = 0.0f;
+  for (int c = 0; c < kHeadC; ++c) s += (float)a[p * kHeadC + c] * w[c];
+  y[p] = s + b[0];
+}
+
+// Head backward: g_a[p, c] = dy[p] w[c]; per-block partial sums of the head
+// weight and bias gradients (part[blk][0..16]).
+__global__ __launch_bounds__(256) void k_head_backward(const bf16 *__restrict__ a, int64_t P,
+                                                       const float *__restrict__ w,
+                                                       const float *__restrict__ dy,
+                                                       float *__restrict__ ga,
+                                                       float *__restrict__ part) {
+  __shared__ float red[256][kHeadC + 1];
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  float d = 0.0f;
+  float av[kHeadC];
+  for (int c = 0; c < kHeadC; ++c) av[c] = 0.0f;
+  if (p < P) {
+    d = dy[p];
+    for (int c = 0; c < kHeadC; ++c) {
+      ga[p * kHeadC + c] = d * w[c];
+      av[c] = (float)a[p * kHeadC + c];
+    }
+  }
+  for (int c = 0; c < kHeadC; ++c) red[threadIdx.x][c] = av[c] * d;
+  red[threadIdx.x][kHeadC] = d;
+  __syncthreads();
+  if (threadIdx.x <= kHeadC) {
+    float s = 0.0f;
+    for (int j = 0; j < 256; ++j) s += red[j][threadIdx.x];
+    part[(int64_t)blockIdx.x * (kHeadC + 1) + threadIdx.x] = s;
+  }
+}
+
+// Squared error: dy = 2 (y - t) / N and per-block partial sums of (y - t)^2.
+__global__ __launch_bounds__(256) void k_mse(const float *__restrict__ y, const float *__restrict__ t,
+                                             int64_t N, float *__restrict__ dy,
+                                             double *__restrict__ part) {
+  __shared__ double red[256];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double e = 0.0;
+  if (i < N) {
+    const float d = y[i] - t[i];
+    dy[i] = 2.0f * d / (float)N;
+    e = (double)d * (double)d;
+  }
+  red[threadIdx.x] = e;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// Adam with bias correction (Kingma & Ba), FP32 master parameters.
+__global__ __launch_bounds__(256) void k_adam(float *__restrict__ w, const float *__restrict__ g,
+                                              float *__restrict__ m, float *__restrict__ v,
+                                              int64_t n, float lr, float b1, float b2, float eps,
+                                              float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+unsigned nblocks(int64_t n) { return (unsigned)((n + 255) / 256); }
+int pad32(int k) { return (k + 31) / 32 * 32; }
+
+}  // namespace
+
+// ===========================================================================
+// Network object
+// ===========================================================================
+
+struct ssp_net {
+  ssp_handle *h = nullptr;
+  int D = 0, H = 0, W = 0, max_batch = 0;
+  int64_t nparam = 0;
+  float *params = nullptr, *grads = nullptr, *adam_m = nullptr, *adam_v = nullptr;
+  int64_t w_off[kLayers], b_off[kLayers], head_w_off = 0, head_b_off = 0;
+  bf16 *wf[kLayers] = {}, *wb[kLayers] = {};
+  int kpf[kLayers], kpb[kLayers];
+  // activations (BF16)
+  bf16 *x0 = nullptr, *a1 = nullptr, *a2 = nullptr, *d1 = nullptr, *a3 = nullptr, *d2 = nullptr,
+       *a4 = nullptr, *c2 = nullptr, *a5 = nullptr, *c1 = nullptr, *a6 = nullptr;
+  // backward scratch
+  float *g_big = nullptr, *g_big2 = nullptr, *g_skip1 = nullptr, *g_skip2 = nullptr;
+  bf16 *dz = nullptr;
+  float *wpart = nullptr, *bpart = nullptr;
+  int64_t wpart_len = 0;
+  double *loss_part = nullptr;
+  float *head_part = nullptr;
+  int batch = 0;  // batch of the last forward
+  std::vector<void *> allocs;
+};
+
+namespace {
+
+int net_alloc(ssp_net *net, void **p, size_t bytes) {
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return SSP_ENOMEM;
+  }
+  net->allocs.push_back(*p);
+  return SSP_OK;
+}
+
+Grid3 grid_level(const ssp_net *n, int level, int batch) {
+  int D = n->D, H = n->H, W = n->W;
+  for (int i = 0; i < level; ++i) {
+    D = (D - 1) / 2 + 1;
+    H = (H - 1) / 2 + 1;
+    W = (W - 1) / 2 + 1;
+  }
+  return Grid3{batch, D, H, W};
+}
+
+template <int MODE>
+int launch_conv(ssp_handle *h, const bf16 *in, int cin, Grid3 gi, Grid3 go, int stride,
+                const bf16 *wt, int kp, const float *bias, int relu, float *out_f, bf16 *out_b,
+                int cout) {
+  const unsigned grid = (unsigned)((go.points() + 63) / 64);
+  switch (cout / 16) {
+    case 1: k_conv_mfma<MODE, 1><<<grid, 256, 0, h->stream>>>(in, cin, gi, go, stride, wt, kp, bias, relu, out_f, out_b); break;
+    case 2: k_conv_mfma<MODE, 2><<<grid, 256, 0, h->stream>>>(in, cin, gi, go, stride, wt, kp, bias, relu, out_f, out_b); break;
+    case 3: k_conv_mfma<MODE, 3><<<grid, 256, 0, h->stream>>>(in, cin, gi, go, stride, wt, kp, bias, relu, out_f, out_b); break;
+    case 5: k_conv_mfma<MODE, 5><<<grid, 256, 0, h->stream>>>(in, cin, gi, go, stride, wt, kp, bias, relu, out_f, out_b); break;
+    default: return fail(h, SSP_EINVAL, "conv: unsupported channel count");
+  }
+  LAUNCHCHK(h);
+  return SSP_OK;
+}
+
+// Forward of conv layer L: out = relu(conv(in) + b) in BF16.
+int layer_forward(ssp_net *n, int L, const bf16 *in, Grid3 gi, Grid3 go, bf16 *out) {
+  const LayerDef &d = kDef[L];
+  return launch_conv<0>(n->h, in, d.ci, gi, go, d.stride, n->wf[L], n->kpf[L],
+                        n->params + n->b_off[L], 1, nullptr, out, d.co);
+}
+
+// Backward of conv layer L given dz (BF16, after the ReLU mask): weight and
+// bias gradients, and (if gx) the FP32 input gradient.
+int layer_backward(ssp_net *n, int L, const bf16 *in, Grid3 gi, Grid3 go, const bf16 *dz,
+                   float *gx) {
+  ssp_handle *h = n->h;
+  const LayerDef &d = kDef[L];
+  const int64_t P = go.points();
+  const int nblk = (int)std::min<int64_t>(256, (P + 255) / 256);
+  const int64_t per = (P + nblk - 1) / nblk;
+  const int64_t m = 27LL * d.ci * d.co;
+  if ((int64_t)nblk * m > n->wpart_len) return fail(h, SSP_EINVAL, "weight-gradient scratch too small");
+  k_conv_wgrad<<<dim3(nblk, 27), 256, 0, h->stream>>>(in, d.ci, gi, go, d.stride, dz, d.co, per,
+                                                      n->wpart, n->bpart);
+  LAUNCHCHK(h);
+  k_sum_blocks<<<nblocks(m), 256, 0, h->stream>>>(n->wpart, nblk, m, n->grads + n->w_off[L]);
+  LAUNCHCHK(h);
+  k_sum_blocks<<<1, 256, 0, h->stream>>>(n->bpart, nblk, d.co, n->grads + n->b_off[L]);
+  LAUNCHCHK(h);
+  if (gx) {
+    int rc = launch_conv<1>(h, dz, d.co, go, gi, d.stride, n->wb[L], n->kpb[L], nullptr, 0, gx,
+                            nullptr, d.ci);
+    if (rc) return rc;
+  }
+  return SSP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ssp_net_create(ssp_handle *h, int D, int H, int W, int max_batch, uint64_t seed,
+                   ssp_net **out) {
+  if (!h || !out) return SSP_EINVAL;
+  *out = nullptr;
+  if (D < 4 || H < 4 || W < 4 || max_batch < 1 || (int64_t)D * H * W * max_batch > (1LL << 28))
+    return fail(h, SSP_EINVAL, "ssp_net_create: invalid grid or batch");
+  HIPCHK(h, hipSetDevice(h->device));
+  ssp_net *n = new (std::nothrow) ssp_net();
+  if (!n) return SSP_ENOMEM;
+  n->h = h;
+  n->D = D;
+  n->H = H;
+  n->W = W;
+  n->max_batch = max_batch;
+  // parameter layout: per layer W[27][Ci][Co] then b[Co]; head w[16], b[1]
+  int64_t off = 0;
+  for (int L = 0; L < kLayers; ++L) {
+    n->w_off[L] = off;
+    off += 27LL * kDef[L].ci * kDef[L].co;
+    n->b_off[L] = off;
+    off += kDef[L].co;
+    n->kpf[L] = pad32(27 * kDef[L].ci);
+    n->kpb[L] = pad32(27 * kDef[L].co);
+  }
+  n->head_w_off = off;
+  off += kHeadC;
+  n->head_b_off = off;
+  off += 1;
+  n->nparam = off;
+  const Grid3 g1 = grid_level(n, 0, max_batch), g2 = grid_level(n, 1, max_batch),
+              g3 = grid_level(n, 2, max_batch);
+  const int64_t P1 = g1.points(), P2 = g2.points(), P3 = g3.points();
+  int rc = SSP_OK;
+  auto A = [&](void **p, size_t bytes) {
+    if (rc == SSP_OK) rc = net_alloc(n, p, bytes);
+  };
+  A((void **)&n->params, sizeof(float) * off);
+  A((void **)&n->grads, sizeof(float) * off);
+  A((void **)&n->adam_m, sizeof(float) * off);
+  A((void **)&n->adam_v, sizeof(float) * off);
+  for (int L = 0; L < kLayers; ++L) {
+    A((void **)&n->wf[L], sizeof(bf16) * kDef[L].co * n->kpf[L]);
+    A((void **)&n->wb[L], sizeof(bf16) * kDef[L].ci * n->kpb[L]);
+  }
+  A((void **)&n->x0, sizeof(bf16) * P1 * 8);
+  A((void **)&n->a1, sizeof(bf16) * P1 * 16);
+  A((void **)&n->a2, sizeof(bf16) * P1 * 16);
+  A((void **)&n->d1, sizeof(bf16) * P2 * 32);
+  A((void **)&n->a3, sizeof(bf16) * P2 * 32);
+  A((void **)&n->d2, sizeof(bf16) * P3 * 48);
+  A((void **)&n->a4, sizeof(bf16) * P3 * 48);
+  A((void **)&n->c2, sizeof(bf16) * P2 * 80);
+  A((void **)&n->a5, sizeof(bf16) * P2 * 32);
+  A((void **)&n->c1, sizeof(bf16) * P1 * 48);
+  A((void **)&n->a6, sizeof(bf16) * P1 * 16);
+  const int64_t big = std::max(P1 * 48, P2 * 80);
+  A((void **)&n->g_big, sizeof(float) * big);
+  A((void **)&n->g_big2, sizeof(float) * big);
+  A((void **)&n->g_skip1, sizeof(float) * P1 * 16);
+  A((void **)&n->g_skip2, sizeof(float) * P2 * 32);
+  A((void **)&n->dz, sizeof(bf16) * std::max(P1 * 16, P2 * 48));
+  n->wpart_len = 256LL * 27 * 80 * 32;
+  A((void **)&n->wpart, sizeof(float) * n->wpart_len);
+  A((void **)&n->bpart, sizeof(float) * 256 * 48);
+  A((void **)&n->loss_part, sizeof(double) * nblocks(P1));
+  A((void **)&n->head_part, sizeof(float) * nblocks(P1) * (kHeadC + 1));
+  if (rc) {
+    ssp_net_destroy(n);
+    return fail(h, rc, "ssp_net_create: allocation failed");
+  }
+  // He-normal initial weights, zero biases (host RNG, seeded)
+  std::vector<float> hp(off, 0.0f);
+  std::mt19937_64 rng(seed);
+  std::normal_distribution<double> nd(0.0, 1.0);
+  for (int L = 0; L < kLayers; ++L) {
+    const double sd = std::sqrt(2.0 / (27.0 * kDef[L].ci));
+    for (int64_t i = 0; i < 27LL * kDef[L].ci * kDef[L].co; ++i)
+      hp[n->w_off[L] + i] = (float)(nd(rng) * sd);
+  }
+  for (int c = 0; c < kHeadC; ++c) hp[n->head_w_off + c] = (float)(nd(rng) * std::sqrt(1.0 / kHeadC));
+  HIPCHK(h, hipMemcpy(n->params, hp.data(), sizeof(float) * off, hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemset(n->grads, 0, sizeof(float) * off));
+  HIPCHK(h, hipMemset(n->adam_m, 0, sizeof(float) * off));
+  HIPCHK(h, hipMemset(n->adam_v, 0, sizeof(float) * off));
+  *out = n;
+  return SSP_OK;
+}
+
+int ssp_net_destroy(ssp_net *n) {
+  if (!n) return SSP_OK;
+  if (n->h) (void)hipStreamSynchronize(n->h->stream);
+  for (void *p : n->allocs) (void)hipFree(p);
+  delete n;
+  return SSP_OK;
+}
+
+int ssp_net_params(ssp_net *n, float **params, float **grads, int64_t *count) {
+  if (!n) return SSP_EINVAL;
+  if (params) *params = n->params;
+  if (grads) *grads = n->grads;
+  if (count) *count = n->nparam;
+  return SSP_OK;
+}
+
+int ssp_net_forward(ssp_net *n, const float *in, int batch, float *out) {
+  if (!n || !in || !out || batch < 1 || batch > n->max_batch) return SSP_EINVAL;
+  ssp_handle *h = n->h;
+  HIPCHK(h, hipSetDevice(h->device));
+  // BF16 GEMM operands from the FP32 master weights
+  for (int L = 0; L < kLayers; ++L) {
+    const int64_t nf = (int64_t)kDef[L].co * n->kpf[L], nb = (int64_t)kDef[L].ci * n->kpb[L];
+    k_pack<<<nblocks(std::max(nf, nb)), 256, 0, h->stream>>>(
+        n->params + n->w_off[L], kDef[L].ci, kDef[L].co, n->wf[L], n->kpf[L], n->wb[L], n->kpb[L]);
+    LAUNCHCHK(h);
+  }
+  const Grid3 g1 = grid_level(n, 0, batch), g2 = grid_level(n, 1, batch), g3 = grid_level(n, 2, batch);
+  k_input<<<nblocks(g1.points()), 256, 0, h->stream>>>(in, g1.points(), n->x0);
+  LAUNCHCHK(h);
+  int rc;
+  if ((rc = layer_forward(n, L_E1A, n->x0, g1, g1, n->a1))) return rc;
+  if ((rc = layer_forward(n, L_E1B, n->a1, g1, g1, n->a2))) return rc;
+  if ((rc = layer_forward(n, L_D1, n->a2, g1, g2, n->d1))) return rc;
+  if ((rc = layer_forward(n, L_E2, n->d1, g2, g2, n->a3))) return rc;
+  if ((rc = layer_forward(n, L_D2, n->a3, g2, g3, n->d2))) return rc;
+  if ((rc = layer_forward(n, L_BOTT, n->d2, g3, g3, n->a4))) return rc;
+  k_up_concat<<<nblocks(g2.points()), 256, 0, h->stream>>>(n->a4, g3, 48, n->a3, 32, g2, n->c2);
+  LAUNCHCHK(h);
+  if ((rc = layer_forward(n, L_U2, n->c2, g2, g2, n->a5))) return rc;
+  k_up_concat<<<nblocks(g1.points()), 256, 0, h->stream>>>(n->a5, g2, 32, n->a2, 16, g1, n->c1);
+  LAUNCHCHK(h);
+  if ((rc = layer_forward(n, L_U1, n->c1, g1, g1, n->a6))) return rc;
+  k_head<<<nblocks(g1.points()), 256, 0, h->stream>>>(n->a6, g1.points(), n->params + n->head_w_off,
+                                                     n->params + n->head_b_off, out);
+  LAUNCHCHK(h);
+  n->batch = batch;
+  return SSP_OK;
+}
+
+int ssp_net_zero_grad(ssp_net *n) {
+  if (!n) return SSP_EINVAL;
+  HIPCHK(n->h, hipMemsetAsync(n->grads, 0, sizeof(float) * n->nparam, n->h->stream));
+  return SSP_OK;
+}
+
+int ssp_net_backward(ssp_net *n, const float *dy) {
+  if (!n || !dy || n->batch < 1) return SSP_EINVAL;
+  ssp_handle *h = n->h;
+  HIPCHK(h, hipSetDevice(h->device));
+  const int batch = n->batch;
+  const Grid3 g1 = grid_level(n, 0, batch), g2 = grid_level(n, 1, batch), g3 = grid_level(n, 2, batch);
+  const int64_t P1 = g1.points(), P2 = g2.points(), P3 = g3.points();
+  int rc;
+  // head
+  float *g_a6 = n->g_big;  // [P1, 16]
+  k_head_backward<<<nblocks(P1), 256, 0, h->stream>>>(n->a6, P1, n->params + n->head_w_off, dy,
+                                                      g_a6, n->head_part);
+  LAUNCHCHK(h);
+  k_sum_blocks<<<1, 256, 0, h->stream>>>(n->head_part, (int)nblocks(P1), kHeadC + 1,
+                                         n->grads + n->head_w_off);
+  LAUNCHCHK(h);
+  // u1: in c1 [P1, 48] -> a6
+  k_relu_grad<<<nblocks(P1 * 16), 256, 0, h->stream>>>(P1, 16, g_a6, 16, 0, nullptr, 0, 0, n->a6, n->dz);
+  LAUNCHCHK(h);
+  float *g_c1 = n->g_big2;  // [P1, 48]
+  if ((rc = layer_backward(n, L_U1, n->c1, g1, g1, n->dz, g_c1))) return rc;
+  // split: channels 0..31 -> up(a5), 32..47 -> a2 (skip)
+  float *g_a5 = n->g_big;  // [P2, 32]
+  k_up_backward<<<nblocks(P2), 256, 0, h->stream>>>(g_c1, g1, 48, 0, 32, g2, g_a5);
+  LAUNCHCHK(h);
+  // the a2 skip gradient, g_c1[:, 32:48], must survive the reuse of g_c1's buffer
+  k_slice<<<nblocks(P1 * 16), 256, 0, h->stream>>>(g_c1, 48, 32, 16, P1, n->g_skip1);
+  LAUNCHCHK(h);
+  k_relu_grad<<<nblocks(P2 * 32), 256, 0, h->stream>>>(P2, 32, g_a5, 32, 0, nullptr, 0, 0, n->a5, n->dz);
+  LAUNCHCHK(h);
+  float *g_c2 = n->g_big2;  // [P2, 80]
+  if ((rc = layer_backward(n, L_U2, n->c2, g2, g2, n->dz, g_c2))) return rc;
+  float *g_a4 = n->g_big;  // [P3, 48]
+  k_up_backward<<<nblocks(P3), 256, 0, h->stream>>>(g_c2, g2, 80, 0, 48, g3, g_a4);
+  LAUNCHCHK(h);
+  k_slice<<<nblocks(P2 * 32), 256, 0, h->stream>>>(g_c2, 80, 48, 32, P2, n->g_skip2);
+  LAUNCHCHK(h);
+  k_relu_grad<<<nblocks(P3 * 48), 256, 0, h->stream>>>(P3, 48, g_a4, 48, 0, nullptr, 0, 0, n->a4, n->dz);
+  LAUNCHCHK(h);
+  float *g_d2 = n->g_big2;  // [P3, 48]
+  if ((rc = layer_backward(n, L_BOTT, n->d2, g3, g3, n->dz, g_d2))) return rc;
+  k_relu_grad<<<nblocks(P3 * 48), 256, 0, h->stream>>>(P3, 48, g_d2, 48, 0, nullptr, 0, 0, n->d2, n->dz);
+  LAUNCHCHK(h);
+  float *g_a3b = n->g_big;  // [P2, 32]
+  if ((rc = layer_backward(n, L_D2, n->a3, g2, g3, n->dz, g_a3b))) return rc;
+  k_relu_grad<<<nblocks(P2 * 32), 256, 0, h->stream>>>(P2, 32, g_a3b, 32, 0, n->g_skip2, 32, 0, n->a3, n->dz);
+  LAUNCHCHK(h);
+  float *g_d1 = n->g_big2;  // [P2, 32]
+  if ((rc = layer_backward(n, L_E2, n->d1, g2, g2, n->dz, g_d1))) return rc;
+  k_relu_grad<<<nblocks(P2 * 32), 256, 0, h->stream>>>(P2, 32, g_d1, 32, 0, nullptr, 0, 0, n->d1, n->dz);
+  LAUNCHCHK(h);
+  float *g_a2b = n->g_big;  // [P1, 16]
+  if ((rc = layer_backward(n, L_D1, n->a2, g1, g2, n->dz, g_a2b))) return rc;
+  k_relu_grad<<<nblocks(P1 * 16), 256, 0, h->stream>>>(P1, 16, g_a2b, 16, 0, n->g_skip1, 16, 0, n->a2, n->dz);
+  LAUNCHCHK(h);
+  float *g_a1 = n->g_big2;  // [P1, 16]
+  if ((rc = layer_backward(n, L_E1B, n->a1, g1, g1, n->dz, g_a1))) return rc;
+  k_relu_grad<<<nblocks(P1 * 16), 256, 0, h->stream>>>(P1, 16, g_a1, 16, 0, nullptr, 0, 0, n->a1, n->dz);
+  LAUNCHCHK(h);
+  if ((rc = layer_backward(n, L_E1A, n->x0, g1, g1, n->dz, nullptr))) return rc;
+  return SSP_OK;
+}
+
+int ssp_net_loss(ssp_net *n, const float *y, const float *target, float *dy, double *loss) {
+  if (!n || !y || !target || !dy || n->batch < 1) return SSP_EINVAL;
+  ssp_handle *h = n->h;
+  const int64_t N = grid_level(n, 0, n->batch).points();
+  const unsigned nb = nblocks(N);
+  k_mse<<<nb, 256, 0, h->stream>>>(y, target, N, dy, n->loss_part);
+  LAUNCHCHK(h);
+  if (loss) {
+    std::vector<double> part(nb);
+    HIPCHK(h, hipMemcpyAsync(part.data(), n->loss_part, sizeof(double) * nb, hipMemcpyDeviceToHost,
+                             h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    double s = 0.0;
+    for (double v : part) s += v;
+    *loss = s / (double)N;
+  }
+  return SSP_OK;
+}
+
+int ssp_net_adam_step(ssp_net *n, float lr, float beta1, float beta2, float eps, int step) {
+  if (!n || step < 1) return SSP_EINVAL;
+  ssp_handle *h = n->h;
+  const float c1 = 1.0f - std::pow(beta1, (float)step), c2 = 1.0f - std::pow(beta2, (float)step);
+  k_adam<<<nblocks(n->nparam), 256, 0, h->stream>>>(n->params, n->grads, n->adam_m, n->adam_v,
+                                                    n->nparam, lr, beta1, beta2, eps, c1, c2);
+  LAUNCHCHK(h);
+  return SSP_OK;
+}
+
+int ssp_net_get_state(ssp_net *n, float *host, int64_t cap) {
+  if (!n || !host || cap < 3 * n->nparam) return SSP_EINVAL;
+  HIPCHK(n->h, hipStreamSynchronize(n->h->stream));
+  HIPCHK(n->h, hipMemcpy(host, n->params, sizeof(float) * n->nparam, hipMemcpyDeviceToHost));
+  HIPCHK(n->h, hipMemcpy(host + n->nparam, n->adam_m, sizeof(float) * n->nparam, hipMemcpyDeviceToHost));
+  HIPCHK(n->h, hipMemcpy(host + 2 * n->nparam, n->adam_v, sizeof(float) * n->nparam, hipMemcpyDeviceToHost));
+  return SSP_OK;
+}
+
+int ssp_net_set_state(ssp_net *n, const float *host, int64_t len) {
+  if (!n || !host || len < n->nparam) return SSP_EINVAL;
+  HIPCHK(n->h, hipStreamSynchronize(n->h->stream));
+  HIPCHK(n->h, hipMemcpy(n->params, host, sizeof(float) * n->nparam, hipMemcpyHostToDevice));
+  if (len >= 3 * n->nparam) {
+    HIPCHK(n->h, hipMemcpy(n->adam_m, host + n->nparam, sizeof(float) * n->nparam, hipMemcpyHostToDevice));
+    HIPCHK(n->h, hipMemcpy(n->adam_v, host + 2 * n->nparam, sizeof(float) * n->nparam, hipMemcpyHostToDevice));
+  }
+  return SSP_OK;
+}
+
+__global__ __launch_bounds__(256) void k_f32_to_bf16(const float *a, int64_t n, bf16 *b) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) b[i] = (bf16)a[i];
+}
+
+// One 3x3x3 convolution on its own (inputs rounded to BF16, FP32 result):
+// mode 0: out = conv(in, w) (no bias, no ReLU), in [B,D,H,W,ci] -> out on the
+// strided grid with co channels; mode 1: out = input gradient of that
+// convolution for the output gradient `in` ([B, Do, Ho, Wo, co]) -> [B,D,H,W,ci].
+// w is FP32 [27][ci][co].  All DEVICE pointers; allocates temporaries.
+int ssp_conv3d(ssp_handle *h, int mode, const float *in, int B, int D, int H, int W, int ci,
+               const float *w, int co, int stride, float *out) {
+  if (!h || !in || !w || !out || (mode != 0 && mode != 1) || (stride != 1 && stride != 2) ||
+      ci % 8 || co % 16 || (mode == 1 && (ci % 16 || co % 8)) || ci > 80 || co > 80)
+    return SSP_EINVAL;
+  HIPCHK(h, hipSetDevice(h->device));
+  const Grid3 gi{B, D, H, W};
+  const Grid3 go{B, (D - 1) / stride + 1, (H - 1) / stride + 1, (W - 1) / stride + 1};
+  const int kpf = pad32(27 * ci), kpb = pad32(27 * co);
+  const int64_t nin = (mode == 0 ? gi.points() * ci : go.points() * co);
+  bf16 *ib = nullptr, *wf = nullptr, *wb = nullptr;
+  HIPCHK(h, hipMalloc(&ib, sizeof(bf16) * nin));
+  HIPCHK(h, hipMalloc(&wf, sizeof(bf16) * co * kpf));
+  HIPCHK(h, hipMalloc(&wb, sizeof(bf16) * ci * kpb));
+  k_f32_to_bf16<<<nblocks(nin), 256, 0, h->stream>>>(in, nin, ib);
+  k_pack<<<nblocks(std::max<int64_t>((int64_t)co * kpf, (int64_t)ci * kpb)), 256, 0, h->stream>>>(
+      w, ci, co, wf, kpf, wb, kpb);
+  int rc = (mode == 0) ? launch_conv<0>(h, ib, ci, gi, go, stride, wf, kpf, nullptr, 0, out, nullptr, co)
+                       : launch_conv<1>(h, ib, co, go, gi, stride, wb, kpb, nullptr, 0, out, nullptr, ci);
+  (void)hipStreamSynchronize(h->stream);
+  (void)hipFree(ib);
+  (void)hipFree(wf);
+  (void)hipFree(wb);
+  return rc;
+}
+
+// Weight and bias gradients of one convolution (inputs rounded to BF16):
+// dw[27][ci][co] = sum_p x[q(p,t), ci] dz[p, co], db[co] = sum_p dz[p, co].
+int ssp_conv3d_wgrad(ssp_handle *h, const float *x, int B, int D, int H, int W, int ci,
+                     const float *dz, int co, int stride, float *dw, float *db) {
+  if (!h || !x || !dz || !dw || !db || (stride != 1 && stride != 2) || ci % 4 || co % 4 ||
+      ci > 80 || co > 48)
+    return SSP_EINVAL;
+  HIPCHK(h, hipSetDevice(h->device));
+  const Grid3 gi{B, D, H, W};
+  const Grid3 go{B, (D - 1) / stride + 1, (H - 1) / stride + 1, (W - 1) / stride + 1};
+  const int64_t P = go.points();
+  const int nblk = (int)std::min<int64_t>(256, (P + 255) / 256);
+  const int64_t per = (P + nblk - 1) / nblk;
+  const int64_t m = 27LL * ci * co;
+  bf16 *xb = nullptr, *db16 = nullptr;
+  float *part = nullptr, *bpart = nullptr;
+  HIPCHK(h, hipMalloc(&xb, sizeof(bf16) * gi.points() * ci));
+  HIPCHK(h, hipMalloc(&db16, sizeof(bf16) * P * co));
+  HIPCHK(h, hipMalloc(&part, sizeof(float) * nblk * m));
+  HIPCHK(h, hipMalloc(&bpart, sizeof(float) * nblk * co));
+  k_f32_to_bf16<<<nblocks(gi.points() * ci), 256, 0, h->stream>>>(x, gi.points() * ci, xb);
+  k_f32_to_bf16<<<nblocks(P * co), 256, 0, h->stream>>>(dz, P * co, db16);
+  HIPCHK(h, hipMemsetAsync(dw, 0, sizeof(float) * m, h->stream));
+  HIPCHK(h, hipMemsetAsync(db, 0, sizeof(float) * co, h->stream));
+  k_conv_wgrad<<<dim3(nblk, 27), 256, 0, h->stream>>>(xb, ci, gi, go, stride, db16, co, per, part,
+                                                      bpart);
+  k_sum_blocks<<<nblocks(m), 256, 0, h->stream>>>(part, nblk, m, dw);
+  k_sum_blocks<<<1, 256, 0, h->stream>>>(bpart, nblk, co, db);
+  const hipError_t e = hipGetLastError();
+  (void)hipStreamSynchronize(h->stream);
+  (void)hipFree(xb);
+  (void)hipFree(db16);
+  (void)hipFree(part);
+  (void)hipFree(bpart);
+  return e == hipSuccess ? SSP_OK : SSP_EHIP;
+}
+
+// Matrix-core self test: D = A B for a 16 x 32 A and a 32 x 16 B (FP32 in
+// and out, BF16 operands), one v_mfma_f32_16x16x32_bf16 with the operand
+// layout the convolutions assume.  DEVICE pointers: A row-major 16 x 32,
+// B row-major 32 x 16, D row-major 16 x 16.
+static __global__ void k_mfma_selftest(const float *A, const float *B, float *D) {
+  const int l = threadIdx.x, m = l % 16, g = l / 16;
+  bf16x8 a, b;
+  for (int j = 0; j < 8; ++j) {
+    a[j] = (bf16)A[m * 32 + 8 * g + j];
+    b[j] = (bf16)B[(8 * g + j) * 16 + m];
+  }
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+  for (int i = 0; i < 4; ++i) D[(4 * g + i) * 16 + m] = acc[i];
+}
+
+int ssp_net_mfma_selftest(ssp_handle *h, const float *A, const float *B, float *D) {
+  if (!h || !A || !B || !D) return SSP_EINVAL;
+  HIPCHK(h, hipSetDevice(h->device));
+  k_mfma_selftest<<<1, 64, 0, h->stream>>>(A, B, D);
+  LAUNCHCHK(h);
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return SSP_OK;
+}
+
+}  // extern "C"

@@ -35,7 +35,10 @@ EXPORTS = (
     "ssp_matrix_destroy", "ssp_set_preconditioner", "ssp_spmv", "ssp_mpk", "ssp_solve",
     "ssp_get_iterations", "ssp_get_residual_history", "ssp_get_true_residual",
     "ssp_get_profile", "ssp_status_string", "ssp_last_error", "ssp_solve_batch",
-    "ssp_autotune_batch",
+    "ssp_autotune_batch", "ssp_net_create", "ssp_net_destroy", "ssp_net_params",
+    "ssp_net_forward", "ssp_net_zero_grad", "ssp_net_backward", "ssp_net_loss",
+    "ssp_net_adam_step", "ssp_net_get_state", "ssp_net_set_state", "ssp_conv3d",
+    "ssp_conv3d_wgrad", "ssp_net_mfma_selftest", "ssp_get_warm_start",
 )
 
 
@@ -59,7 +62,8 @@ class _Opts(C.Structure):
                 ("max_refine", C.c_int), ("check_every", C.c_int), ("fixed_outer", C.c_int),
                 ("profile", C.c_int), ("trace_cap", C.c_int),
                 ("trace_vm", C.c_void_p), ("trace_alpha", C.c_void_p),
-                ("trace_beta", C.c_void_p), ("trace_W", C.c_void_p)]
+                ("trace_beta", C.c_void_p), ("trace_W", C.c_void_p),
+                ("warm_start", C.c_int)]
 
 
 _lib = None
@@ -101,10 +105,24 @@ def load():
         "ssp_get_iterations": (i32, [vp, C.POINTER(i32), C.POINTER(i32)]),
         "ssp_get_residual_history": (i32, [vp, vp, i32, C.POINTER(i32)]),
         "ssp_get_true_residual": (i32, [vp, C.POINTER(dbl)]),
+        "ssp_get_warm_start": (i32, [vp, C.POINTER(i32), C.POINTER(dbl)]),
         "ssp_get_profile": (i32, [vp, vp, vp]),
         "ssp_solve_batch": (i32, [vp, i32, vp, vp, vp, i32, dbl, i32, C.POINTER(_Opts),
                                   C.POINTER(Tune), vp, vp, vp]),
         "ssp_autotune_batch": (i32, [vp, i32, vp, vp, i32, C.c_char_p, C.POINTER(Tune)]),
+        "ssp_net_create": (i32, [vp, i32, i32, i32, i32, C.c_uint64, C.POINTER(vp)]),
+        "ssp_net_destroy": (i32, [vp]),
+        "ssp_net_params": (i32, [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(i64)]),
+        "ssp_net_forward": (i32, [vp, vp, i32, vp]),
+        "ssp_net_zero_grad": (i32, [vp]),
+        "ssp_net_backward": (i32, [vp, vp]),
+        "ssp_net_loss": (i32, [vp, vp, vp, vp, C.POINTER(dbl)]),
+        "ssp_net_adam_step": (i32, [vp, C.c_float, C.c_float, C.c_float, C.c_float, i32]),
+        "ssp_net_get_state": (i32, [vp, vp, i64]),
+        "ssp_net_set_state": (i32, [vp, vp, i64]),
+        "ssp_conv3d": (i32, [vp, i32, vp, i32, i32, i32, i32, i32, vp, i32, i32, vp]),
+        "ssp_conv3d_wgrad": (i32, [vp, vp, i32, i32, i32, i32, i32, vp, i32, i32, vp, vp]),
+        "ssp_net_mfma_selftest": (i32, [vp, vp, vp, vp]),
         "ssp_status_string": (C.c_char_p, [i32]),
         "ssp_last_error": (C.c_char_p, [vp]),
     }
@@ -145,6 +163,8 @@ class SolveResult:
     hist: np.ndarray
     trace: Optional[dict] = None
     profile: Optional[dict] = None
+    warm_kept: int = -1          # 1 warm start used, 0 fell back to x0 = 0, -1 none
+    warm_rel0: float = float("nan")
 
     @property
     def ok(self):
@@ -217,6 +237,7 @@ class Handle:
         self.stream = stream
         self._h = C.c_void_p()
         self._matrices = weakref.WeakSet()
+        self._nets = weakref.WeakSet()
         rc = lib.ssp_create(C.byref(self._h), device, C.c_void_p(stream.cuda_stream))
         if rc:
             raise SspError(rc, "ssp_create")
@@ -230,6 +251,8 @@ class Handle:
     def close(self):
         if self._h:
             for m in list(self._matrices):
+                m.close()
+            for m in list(self._nets):
                 m.close()
             load().ssp_destroy(self._h)
             self._h = C.c_void_p()
@@ -361,13 +384,15 @@ class Handle:
     def solve(self, A: Matrix, b, x, s: int = 4, rtol: float = 1e-8, maxit: int = 10000,
               method: str = "sstep", precision: str = "fp64", inner_rtol: float = 1e-5,
               max_refine: int = 10, check_every: int = 0, fixed_outer: int = 0,
-              profile: bool = False, trace_cap: int = 0) -> SolveResult:
+              profile: bool = False, trace_cap: int = 0,
+              warm_start: bool = False) -> SolveResult:
         import torch
         _check_dev(b, torch.float64, A.n, "b")
         _check_dev(x, torch.float64, A.n, "x")
         o = _Opts(method=METHOD[method], precision=PRECISION[precision], inner_rtol=inner_rtol,
                   max_refine=max_refine, check_every=check_every, fixed_outer=fixed_outer,
-                  profile=1 if profile else 0, trace_cap=0)
+                  profile=1 if profile else 0, trace_cap=0,
+                  warm_start=1 if warm_start else 0)
         trace = None
         if trace_cap > 0:
             trace = dict(vm=np.zeros((trace_cap, 2 * s)), alpha=np.zeros((trace_cap, s)),
@@ -398,5 +423,169 @@ class Handle:
             prof = dict(launches=list(launches), ms=list(ms))
         if trace is not None:
             trace = {k: v[:outer.value] for k, v in trace.items()}
+        kept, rel0 = C.c_int(), C.c_double()
+        lib.ssp_get_warm_start(self._h, C.byref(kept), C.byref(rel0))
         return SolveResult(status=rc, outer=outer.value, cg_equiv=cge.value, true_rel=tr.value,
-                           hist=hist, trace=trace, profile=prof)
+                           hist=hist, trace=trace, profile=prof, warm_kept=kept.value,
+                           warm_rel0=rel0.value)
+
+    # ---------------------------------------------------------------- network
+    def net(self, shape, max_batch: int = 1, seed: int = 0) -> "Net":
+        """The warm-start network for grids of `shape` (D, H, W)."""
+        D, H, W = shape
+        out = C.c_void_p()
+        rc = load().ssp_net_create(self._h, D, H, W, max_batch, seed, C.byref(out))
+        if rc:
+            self._err(rc, "ssp_net_create")
+        return Net(self, out, tuple(shape), max_batch)
+
+    def conv3d(self, x, w, stride=1, mode=0):
+        """One 3x3x3 convolution (mode 0) or its input gradient (mode 1) on the
+        matrix cores.  x: float32 [B, D, H, W, C]; w: float32 [27, Ci, Co]."""
+        import torch
+        w = w.contiguous()
+        _, ci, co = w.shape
+        B, D, H, W, C_ = x.shape
+        if mode == 0:
+            assert C_ == ci
+            shp = (B,) + tuple((n - 1) // stride + 1 for n in (D, H, W)) + (co,)
+            grid = (D, H, W)
+        else:
+            raise ValueError("use conv3d_input_grad")
+        out = torch.empty(shp, device=x.device, dtype=torch.float32)
+        _check_dev(x, torch.float32, name="x")
+        _check_dev(w, torch.float32, name="w")
+        rc = load().ssp_conv3d(self._h, 0, _ptr(x), B, *grid, ci, _ptr(w), co, stride, _ptr(out))
+        if rc:
+            self._err(rc, "ssp_conv3d")
+        return out
+
+    def conv3d_input_grad(self, dy, w, in_shape, stride=1):
+        """Input gradient of conv3d for the output gradient dy [B, Do, Ho, Wo, Co];
+        in_shape = (D, H, W) of the convolution's input."""
+        import torch
+        w = w.contiguous()
+        _, ci, co = w.shape
+        B = dy.shape[0]
+        out = torch.empty((B,) + tuple(in_shape) + (ci,), device=dy.device, dtype=torch.float32)
+        _check_dev(dy, torch.float32, name="dy")
+        _check_dev(w, torch.float32, name="w")
+        rc = load().ssp_conv3d(self._h, 1, _ptr(dy), B, *in_shape, ci, _ptr(w), co, stride,
+                               _ptr(out))
+        if rc:
+            self._err(rc, "ssp_conv3d")
+        return out
+
+    def conv3d_wgrad(self, x, dy, stride=1):
+        """(dw [27, Ci, Co], db [Co]) of conv3d for input x and output gradient dy."""
+        import torch
+        B, D, H, W, ci = x.shape
+        co = dy.shape[-1]
+        dw = torch.empty((27, ci, co), device=x.device, dtype=torch.float32)
+        db = torch.empty((co,), device=x.device, dtype=torch.float32)
+        _check_dev(x, torch.float32, name="x")
+        _check_dev(dy, torch.float32, name="dy")
+        rc = load().ssp_conv3d_wgrad(self._h, _ptr(x), B, D, H, W, ci, _ptr(dy), co, stride,
+                                     _ptr(dw), _ptr(db))
+        if rc:
+            self._err(rc, "ssp_conv3d_wgrad")
+        return dw, db
+
+    def mfma_selftest(self, A, B):
+        """D = A B (16x32 by 32x16, BF16 operands) with one matrix-core instruction."""
+        import torch
+        D = torch.empty((16, 16), device=A.device, dtype=torch.float32)
+        _check_dev(A, torch.float32, 512, "A")
+        _check_dev(B, torch.float32, 512, "B")
+        rc = load().ssp_net_mfma_selftest(self._h, _ptr(A), _ptr(B), _ptr(D))
+        if rc:
+            self._err(rc, "ssp_net_mfma_selftest")
+        return D
+
+
+class Net:
+    """The warm-start U-Net (ssp_net_*): parameters, forward, backward, Adam."""
+
+    def __init__(self, handle, ptr, shape, max_batch):
+        self.handle = handle
+        self._p = ptr
+        self.shape = shape
+        self.max_batch = max_batch
+        handle._nets.add(self)
+        pp, gp, cnt = C.c_void_p(), C.c_void_p(), C.c_int64()
+        load().ssp_net_params(self._p, C.byref(pp), C.byref(gp), C.byref(cnt))
+        self.count = cnt.value
+        self._pp, self._gp = pp.value, gp.value
+        self.step = 0
+
+    def _rc(self, rc, what):
+        if rc:
+            self.handle._err(rc, what)
+
+    def params(self):
+        """Zero-copy float32 views of the parameters and their gradients."""
+        import torch
+        dev = "cuda:%d" % self.handle.device
+        p = torch.as_tensor(_DeviceArray(self._pp, self.count, "<f4"), device=dev)
+        g = torch.as_tensor(_DeviceArray(self._gp, self.count, "<f4"), device=dev)
+        return p, g
+
+    def forward(self, inp, out=None):
+        """inp: float32 [B, D, H, W, 2] (log k, f) -> float32 [B, D, H, W]."""
+        import torch
+        B = inp.shape[0]
+        if tuple(inp.shape[1:]) != self.shape + (2,):
+            raise ValueError("input must be [B, %d, %d, %d, 2]" % self.shape)
+        _check_dev(inp, torch.float32, name="inp")
+        if out is None:
+            out = torch.empty((B,) + self.shape, device=inp.device, dtype=torch.float32)
+        _check_dev(out, torch.float32, inp.numel() // 2, "out")
+        self._rc(load().ssp_net_forward(self._p, _ptr(inp), B, _ptr(out)), "ssp_net_forward")
+        return out
+
+    def loss(self, y, target, dy=None):
+        """Mean squared error of the last forward's output; returns (loss, dy)."""
+        import torch
+        if dy is None:
+            dy = torch.empty_like(y)
+        _check_dev(y, torch.float32, name="y")
+        _check_dev(target, torch.float32, y.numel(), "target")
+        v = C.c_double()
+        self._rc(load().ssp_net_loss(self._p, _ptr(y), _ptr(target), _ptr(dy), C.byref(v)),
+                 "ssp_net_loss")
+        return v.value, dy
+
+    def zero_grad(self):
+        self._rc(load().ssp_net_zero_grad(self._p), "ssp_net_zero_grad")
+
+    def backward(self, dy):
+        import torch
+        _check_dev(dy, torch.float32, name="dy")
+        self._rc(load().ssp_net_backward(self._p, _ptr(dy)), "ssp_net_backward")
+
+    def adam_step(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        self.step += 1
+        self._rc(load().ssp_net_adam_step(self._p, lr, b1, b2, eps, self.step), "ssp_net_adam_step")
+
+    def get_state(self) -> np.ndarray:
+        """Parameters and Adam moments, float32 [3, count]."""
+        out = np.zeros(3 * self.count, dtype=np.float32)
+        self._rc(load().ssp_net_get_state(self._p, out.ctypes.data_as(C.c_void_p), out.size),
+                 "ssp_net_get_state")
+        return out.reshape(3, self.count)
+
+    def set_state(self, state):
+        arr = np.ascontiguousarray(np.asarray(state, dtype=np.float32).reshape(-1))
+        self._rc(load().ssp_net_set_state(self._p, arr.ctypes.data_as(C.c_void_p), arr.size),
+                 "ssp_net_set_state")
+
+    def close(self):
+        if self._p and self.handle._h:
+            load().ssp_net_destroy(self._p)
+        self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -147,3 +147,70 @@ def fourier_source(shape, seed: int, modes: int = 16) -> np.ndarray:
 def batch_sides(seed: int, count: int = 32, lo: int = 32, hi: int = 160) -> np.ndarray:
     """Side lengths L_i ~ U{lo..hi} for a batch of cubic grids."""
     return rng(seed).integers(lo, hi + 1, size=count)
+
+
+# ---------------------------------------------------------------------------
+# Device-side generators for large sample sets (same definitions as the host
+# ones above; the noise comes from torch's seeded device generator, so values
+# differ from the host versions but follow the same distribution).
+# ---------------------------------------------------------------------------
+
+_SPEC_CACHE = {}
+
+
+def gaussian_random_field_device(shape, sigma: float, ell: float, seed: int, device="cuda"):
+    """gaussian_random_field() on the device (torch FFTs; float64 tensor of
+    n entries, x fastest)."""
+    import torch
+    nx, ny, nz = _grid(shape)
+    ext = (2 * nz, 2 * ny, 2 * nx)            # (z, y, x): x fastest in memory
+    key = (ext, float(ell), str(device))
+    spec = _SPEC_CACHE.get(key)
+    if spec is None:
+        h = 1.0 / (max(nx, ny, nz) + 1)
+        fz = torch.fft.fftfreq(ext[0], d=h, dtype=torch.float64, device=device)
+        fy = torch.fft.fftfreq(ext[1], d=h, dtype=torch.float64, device=device)
+        fx = torch.fft.rfftfreq(ext[2], d=h, dtype=torch.float64, device=device)
+        k2 = (fz[:, None, None] ** 2 + fy[None, :, None] ** 2 + fx[None, None, :] ** 2) \
+            * (2.0 * np.pi) ** 2
+        spec = torch.exp(-0.25 * k2 * ell * ell)
+        _SPEC_CACHE[key] = spec
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    noise = torch.randn(ext, generator=gen, device=device, dtype=torch.float64)
+    field = torch.fft.irfftn(torch.fft.rfftn(noise) * spec, s=ext)
+    field = field[:nz, :ny, :nx].contiguous()
+    field = field - field.mean()
+    field = field * (sigma / torch.clamp(field.std(unbiased=False), min=1e-300))
+    return field.reshape(-1)
+
+
+def fourier_source_device(shape, seed: int, modes: int = 16, device="cuda"):
+    """fourier_source() on the device (same coefficients, float64 tensor)."""
+    import torch
+    nx, ny, nz = _grid(shape)
+    g = rng(seed)
+    a = g.standard_normal(modes)
+    kap = g.integers(1, 5, size=(modes, 3))
+    xs = [(torch.arange(m, dtype=torch.float64, device=device) + 1.0) / (m + 1.0)
+          for m in (nx, ny, nz)]
+    f = torch.zeros((nz, ny, nx), dtype=torch.float64, device=device)
+    for m in range(modes):
+        sx = torch.sin(np.pi * float(kap[m, 0]) * xs[0])
+        sy = torch.sin(np.pi * float(kap[m, 1]) * xs[1])
+        sz = torch.sin(np.pi * float(kap[m, 2]) * xs[2])
+        f += float(a[m]) * sz[:, None, None] * sy[None, :, None] * sx[None, None, :]
+    return f.reshape(-1)
+
+
+def warm_start_problem(shape, seed: int, sigma: float = 1.0, ell: float = 0.1, device="cuda"):
+    """One variable-coefficient Poisson problem -div(k grad u) = f on the unit
+    cube's interior grid: log k a Gaussian random field, f a random sum of
+    Fourier modes, and b = h^2 f for the unscaled 3d7_vark operator
+    (h = 1 / (N + 1)).  Returns float64 device tensors (log k, k, f, b)."""
+    import torch
+    nx, ny, nz = _grid(shape)
+    logk = gaussian_random_field_device(shape, sigma, ell, 2 * seed, device)
+    f = fourier_source_device(shape, 2 * seed + 1, device=device)
+    h = 1.0 / (max(nx, ny, nz) + 1)
+    return logk, torch.exp(logk), f, f * (h * h)

@@ -1,0 +1,79 @@
+"""The warm-start judge in ssp_solve and the learned warm start end to end.
+
+The judge keeps a given x0 only when ||b - A x0|| < ||b||; otherwise the
+solve starts from x0 = 0 and must then equal the plain zero-guess solve bit
+for bit.
+"""
+import numpy as np
+import pytest
+
+from paper_2501_03743_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+SHAPE = (20, 18, 16)
+
+
+@pytest.fixture(scope="module")
+def H():
+    from paper_2501_03743_amd import sstep
+    with sstep.Handle(0) as h:
+        yield h
+
+
+@pytest.fixture(scope="module")
+def problem(H):
+    logk, k, f, b = wl.warm_start_problem(SHAPE, 3)
+    A = H.matrix_stencil("3d7_vark", SHAPE, k=k)
+    x = torch.zeros_like(b)
+    ref = H.solve(A, b, x, s=4, rtol=1e-8)
+    assert ref.status == 0 and ref.warm_kept == -1
+    yield A, b, x, ref, k
+    A.close()
+
+
+@pytest.mark.parametrize("method", ["sstep", "pcg"])
+def test_bad_guess_falls_back_to_zero_bitwise(H, problem, method):
+    A, b, xsol, ref, _ = problem
+    x_ref = torch.zeros_like(b)
+    r_ref = H.solve(A, b, x_ref, s=4, rtol=1e-8, method=method)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1)
+    x = 10.0 * torch.randn(b.shape, generator=g, device="cuda", dtype=torch.float64)
+    r = H.solve(A, b, x, s=4, rtol=1e-8, method=method, warm_start=True)
+    assert r.warm_kept == 0 and r.warm_rel0 >= 1.0
+    assert r.status == 0 and r.outer == r_ref.outer
+    assert torch.equal(x, x_ref)
+
+
+def test_nonfinite_guess_falls_back(H, problem):
+    A, b, _, ref, _ = problem
+    x = torch.zeros_like(b)
+    x[17] = float("nan")
+    r = H.solve(A, b, x, s=4, rtol=1e-8, warm_start=True)
+    assert r.warm_kept == 0 and r.status == 0 and r.outer == ref.outer
+    assert bool(torch.isfinite(x).all())
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed_ir"])
+def test_good_guess_is_kept_and_saves_iterations(H, problem, precision):
+    A, b, xsol, ref, _ = problem
+    g = torch.Generator(device="cuda")
+    g.manual_seed(2)
+    # the solution with a smooth relative perturbation of 1e-3
+    pert = wl.gaussian_random_field_device(SHAPE, 1e-3, 0.2, 7)
+    x = xsol * (1.0 + pert)
+    r = H.solve(A, b, x, s=4, rtol=1e-8, precision=precision, warm_start=True)
+    assert r.warm_kept == 1 and r.warm_rel0 < 1.0
+    assert r.status == 0 and r.true_rel <= 1.5e-8
+    base = H.solve(A, b, torch.zeros_like(b), s=4, rtol=1e-8, precision=precision)
+    assert r.outer < base.outer, (r.outer, base.outer)
+
+
+def test_exact_guess_converges_immediately(H, problem):
+    A, b, xsol, ref, _ = problem
+    x = xsol.clone()
+    r = H.solve(A, b, x, s=4, rtol=1e-8, warm_start=True)
+    assert r.warm_kept == 1 and r.outer == 0 and r.status == 0
+    assert torch.equal(x, xsol)
