@@ -102,7 +102,13 @@ typedef struct ssp_opts {
   int warm_start;      /* 1: x holds a predicted initial guess (e.g. the warm-
                           start network's); it is judged by its true residual
                           before the solve and replaced by x = 0 when
-                          ||b - A x|| >= ||b|| (see ssp_get_warm_start)         */
+                          ||b - A x|| >= ||b|| or not finite (see
+                          ssp_get_warm_start)                                   */
+  int warm_sweeps;     /* warm start only: damped Jacobi sweeps
+                          x += omega B^-1 (b - A x) applied to the guess before
+                          it is judged (removes its rough, high-residual part);
+                          0 = none                                              */
+  double warm_omega;   /* damping of those sweeps; 0 = 2/3                      */
 } ssp_opts;
 
 /* ---- handle ---------------------------------------------------------------- */
@@ -187,7 +193,8 @@ int ssp_get_iterations(const ssp_handle *h, int *outer, int *cg_equiv);
 
 /* Outcome of the last solve's warm-start judge (opts.warm_start = 1):
  * *kept = 1 if the given x was used, 0 if it fell back to x = 0, -1 if the
- * last solve had no warm start; *rel0 = ||b - A x_given|| / ||b||. */
+ * last solve had no warm start; *rel0 = ||b - A x0|| / ||b|| of the guess as
+ * judged (after the smoothing sweeps). */
 int ssp_get_warm_start(const ssp_handle *h, int *kept, double *rel0);
 
 /* ||r_i||_2/||b||_2 of the last solve, i = 0 (initial) .. outer; copies at most

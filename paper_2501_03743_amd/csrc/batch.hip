@@ -75,7 +75,7 @@ int ssp_solve_batch(ssp_handle *h, int nsys, const ssp_matrix *const *A, const d
     if (rc) return rc;
     Layout &l = L[i];
     l.n = A[i]->n;
-    l.ld = (l.n + 63) / 64 * 64;
+    l.ld = (l.n + 63) / 64 * 64 + kColumnStagger / (int64_t)sizeof(float);
     if (trq <= 0) {
       // the partition of a single solve: results equal ssp_solve's bit for bit
       const int G = grid_rows(l.n);

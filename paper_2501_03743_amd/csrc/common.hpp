@@ -12,6 +12,7 @@ constexpr int kWG = 256;          // threads per workgroup of every streaming ke
 constexpr int kWave = 64;         // CDNA wavefront
 constexpr int kXcd = 8;           // MI355X: 8 accelerator dies, round-robin dispatch
 constexpr int kGridMax = 2048;    // workgroups of a streaming launch (8 per CU)
+constexpr int64_t kColumnStagger = 17 * 256;  // bytes added to block leading dimensions
 constexpr int kCsrLds = 4096;     // FP64 products staged in LDS per CSR row block
 constexpr int kCsrRowsMax = 1024; // rows per CSR row block
 

@@ -236,6 +236,24 @@ struct EpiWarmCheck {
   }
 };
 
+// One damped Jacobi sweep xout = xin + omega B^-1 (b - A xin) (smooths a
+// predicted initial guess before it is judged).
+struct EpiJacobiSweep {
+  static constexpr int NP = 0;
+  static constexpr bool kCheck = false;
+  const double *b, *xin;
+  double *xout;
+  Prec<double> pc;
+  double omega;
+  __device__ __forceinline__ void row(int64_t i, double v, double *) const {
+#pragma clang fp contract(off)
+    const double t = pc.apply(i, b[i] - v);
+    const double u = omega * t;
+    xout[i] = xin[i] + u;
+  }
+  __device__ __forceinline__ void finish(DevState *, const double *) const {}
+};
+
 // Iterative refinement, outer step: the FP64 residual r = b - A x of the
 // current FP64 iterate, rounded to FP32 as the right-hand side of the next
 // inner solve; the inner iterate d starts at 0, so the inner residual is that

@@ -134,59 +134,18 @@ __device__ __forceinline__ T csr_row_sum(const CsrArgs<T> &A, const T *__restric
 struct NoPre {};
 
 // One thread per row over rows [r0, r1) (consecutive rows in consecutive
-// threads), two rows per thread per step: the row pointers, entries and
-// gathers of both rows are in flight together, and so are the loads the
-// epilogue needs (pre(i), issued before the gathers).  No LDS, no barriers;
-// suits short rows.  Each row's sum has the same order and rounding as a
-// sequential product, and the epilogue sees the rows in the same order as
-// with one row per step.
+// threads): the epilogue's loads (pre(i)) and the row's first U entries and
+// their gathers are all issued before any product is summed.  No LDS, no
+// barriers; suits short rows.  Each row's sum has the same order and rounding
+// as a sequential product.
 template <typename T, class Pre, class F>
 __device__ __forceinline__ void csr_rows_direct(const CsrArgs<T> &A, const T *__restrict__ x,
                                                 int64_t r0, int64_t r1, Pre &&pre, F &&f) {
-#pragma clang fp contract(off)
   constexpr int U = 8;
-  int64_t row = r0 + threadIdx.x;
-  for (; row + kWG < r1; row += 2 * kWG) {
-    const int64_t row2 = row + kWG;
-    const int a1 = A.rowptr[row], b1 = A.rowptr[row + 1];
-    const int a2 = A.rowptr[row2], b2 = A.rowptr[row2 + 1];
-    const auto p1 = pre(row);
-    const auto p2 = pre(row2);
-    if (b1 - a1 <= U && b2 - a2 <= U) {
-      int c1[U], c2[U];
-      T v1[U], v2[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if (a1 + u < b1) {
-          c1[u] = A.colind[a1 + u];
-          v1[u] = A.val[a1 + u];
-        }
-        if (a2 + u < b2) {
-          c2[u] = A.colind[a2 + u];
-          v2[u] = A.val[a2 + u];
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if (a1 + u < b1) v1[u] = v1[u] * x[c1[u]];
-        if (a2 + u < b2) v2[u] = v2[u] * x[c2[u]];
-      }
-      T s1 = 0, s2 = 0;
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if (a1 + u < b1) s1 += v1[u];
-        if (a2 + u < b2) s2 += v2[u];
-      }
-      f(row, s1, p1);
-      f(row2, s2, p2);
-    } else {
-      f(row, csr_row_sum<T, U>(A, x, a1, b1), p1);
-      f(row2, csr_row_sum<T, U>(A, x, a2, b2), p2);
-    }
-  }
-  if (row < r1) {
-    const auto p1 = pre(row);
-    f(row, csr_row_sum<T, U>(A, x, A.rowptr[row], A.rowptr[row + 1]), p1);
+  for (int64_t row = r0 + threadIdx.x; row < r1; row += kWG) {
+    const int a = A.rowptr[row], b = A.rowptr[row + 1];
+    const auto p = pre(row);
+    f(row, csr_row_sum<T, U>(A, x, a, b), p);
   }
 }
 

@@ -154,84 +154,113 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const bf16 *__restrict__ in, 
   }
 }
 
-// Weight gradient of one tap block: part[blk][t][ci][co] = sum over the
-// block's output points of x[q(p, t), ci] * dz[p, co] (FP32, fixed order).
-// Each thread owns a 4 x 4 (ci, co) register block.
-__global__ __launch_bounds__(256) void k_conv_wgrad(const bf16 *__restrict__ xin, int ci_n,
+// Weight and bias gradients of one tap on the matrix cores: a GEMM with
+// M = ci, N = co and K = the block's output points,
+//   part[blk][t][ci][co] = sum_p x[q_t(p), ci] dz[p, co].
+// Points are staged KC at a time in LDS transposed to [channel][point]
+// (BF16), so a lane's operand (8 consecutive points of one channel) is one
+// 16-byte LDS read; the 16 x 16 output tiles are spread over the four waves
+// (TPW tiles per wave).  ci is padded to 16 with zero rows.  Tap-0 blocks
+// also sum dz per channel for the bias gradient (bpart[blk][co]).
+template <int TPW>
+__global__ __launch_bounds__(256) void k_wgrad_mfma(const bf16 *__restrict__ xin, int ci_n,
                                                     Grid3 gi, Grid3 go, int stride,
                                                     const bf16 *__restrict__ dz, int co_n,
                                                     int64_t pts_per_blk, float *__restrict__ part,
                                                     float *__restrict__ bpart) {
-  constexpr int TP = 32;  // points staged per step
-  __shared__ float sx[TP][80 + 1];
-  __shared__ float sd[TP][48 + 1];
+  constexpr int KC = 64;        // points per staged chunk (two k-steps)
+  constexpr int LDP = KC + 8;   // padded LDS row, in BF16 elements
+  __shared__ __align__(16) bf16 sx[80][LDP];
+  __shared__ __align__(16) bf16 sd[48][LDP];
   const int t = blockIdx.y;
   const int dz_ = t / 9 - 1, dy_ = (t / 3) % 3 - 1, dx_ = t % 3 - 1;
-  const int nci4 = ci_n / 4, nco4 = co_n / 4;
-  const int my = threadIdx.x;
-  const bool active = my < nci4 * nco4;
-  const int ci0 = active ? (my / nco4) * 4 : 0, co0 = active ? (my % nco4) * 4 : 0;
-  float acc[4][4] = {};
-  float bacc = 0.0f;   // tap-0 blocks: bias gradient of channel threadIdx.x
+  const int cim = (ci_n + 15) / 16 * 16;
+  const int NN = co_n / 16, ntile = (cim / 16) * NN;
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  const int m = lane % 16, g = lane / 16;
+  f32x4 acc[TPW];
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float bacc = 0.0f;
   const int64_t P = go.points();
   const int64_t p0 = (int64_t)blockIdx.x * pts_per_blk;
   const int64_t p1 = p0 + pts_per_blk < P ? p0 + pts_per_blk : P;
-  for (int64_t pb = p0; pb < p1; pb += TP) {
-    for (int e = threadIdx.x; e < TP * ci_n; e += 256) {
-      const int j = e / ci_n, c = e - j * ci_n;
+  for (int e = threadIdx.x; e < (cim - ci_n) * LDP; e += 256)
+    sx[ci_n + e / LDP][e % LDP] = (bf16)0.0f;
+  const bf16x8 zero8 = {};
+  const int ngx = ci_n / 8, ngd = co_n / 8;
+  for (int64_t pb = p0; pb < p1; pb += KC) {
+    for (int e = threadIdx.x; e < KC * ngx; e += 256) {
+      const int j = e / ngx, cg = e - j * ngx;
       const int64_t p = pb + j;
-      float v = 0.0f;
+      bf16x8 v = zero8;
       if (p < p1) {
         int b, z, y, x;
         decode(p, go, b, z, y, x);
         const int qz = stride * z + dz_, qy = stride * y + dy_, qx = stride * x + dx_;
         if (qz >= 0 && qz < gi.D && qy >= 0 && qy < gi.H && qx >= 0 && qx < gi.W)
-          v = (float)xin[encode(b, qz, qy, qx, gi) * ci_n + c];
+          v = *(const bf16x8 *)(xin + encode(b, qz, qy, qx, gi) * ci_n + cg * 8);
       }
-      sx[j][c] = v;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) sx[cg * 8 + u][j] = v[u];
     }
-    for (int e = threadIdx.x; e < TP * co_n; e += 256) {
-      const int j = e / co_n, c = e - j * co_n;
+    for (int e = threadIdx.x; e < KC * ngd; e += 256) {
+      const int j = e / ngd, cg = e - j * ngd;
       const int64_t p = pb + j;
-      sd[j][c] = (p < p1) ? (float)dz[p * co_n + c] : 0.0f;
+      const bf16x8 v = (p < p1) ? *(const bf16x8 *)(dz + p * co_n + cg * 8) : zero8;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) sd[cg * 8 + u][j] = v[u];
     }
     __syncthreads();
     if (t == 0 && threadIdx.x < co_n)
-      for (int j = 0; j < TP; ++j) bacc += sd[j][threadIdx.x];
-    if (active) {
-      for (int j = 0; j < TP; ++j) {
-        float xv[4], dv[4];
+      for (int j = 0; j < KC; ++j) bacc += (float)sd[threadIdx.x][j];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          xv[u] = sx[j][ci0 + u];
-          dv[u] = sd[j][co0 + u];
+    for (int i = 0; i < TPW; ++i) {
+      const int tile = wave + 4 * i;
+      if (tile < ntile) {
+        const int mi = tile / NN, ni = tile - (tile / NN) * NN;
+#pragma unroll
+        for (int ks = 0; ks < KC; ks += 32) {
+          const bf16x8 a = *(const bf16x8 *)&sx[mi * 16 + m][ks + 8 * g];
+          const bf16x8 bb = *(const bf16x8 *)&sd[ni * 16 + m][ks + 8 * g];
+          acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bb, acc[i], 0, 0, 0);
         }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) acc[u][v] += xv[u] * dv[v];
       }
     }
     __syncthreads();
   }
   if (t == 0 && threadIdx.x < co_n) bpart[(int64_t)blockIdx.x * co_n + threadIdx.x] = bacc;
-  if (active) {
-    float *o = part + ((int64_t)blockIdx.x * 27 + t) * ci_n * co_n;
+  float *o = part + ((int64_t)blockIdx.x * 27 + t) * ci_n * co_n;
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+  for (int i = 0; i < TPW; ++i) {
+    const int tile = wave + 4 * i;
+    if (tile < ntile) {
+      const int mi = tile / NN, ni = tile - (tile / NN) * NN;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) o[(ci0 + u) * co_n + co0 + v] = acc[u][v];
+      for (int r = 0; r < 4; ++r) {
+        const int ci = mi * 16 + 4 * g + r;
+        if (ci < ci_n) o[ci * co_n + ni * 16 + m] = acc[i][r];
+      }
+    }
   }
 }
 
-// grad[i] += sum over blocks of part[blk][i] (fixed order).
+// grad[i] += sum over blocks of part[blk][i] (fixed order: four running
+// sums over blocks k = 0, 1, 2, 3 mod 4, then combined).
 __global__ __launch_bounds__(256) void k_sum_blocks(const float *__restrict__ part, int nblk,
                                                     int64_t m, float *__restrict__ grad) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= m) return;
-  float s = 0.0f;
-  for (int k = 0; k < nblk; ++k) s += part[(int64_t)k * m + i];
-  grad[i] += s;
+  float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
+  int k = 0;
+  for (; k + 4 <= nblk; k += 4) {
+    s0 += part[(int64_t)k * m + i];
+    s1 += part[(int64_t)(k + 1) * m + i];
+    s2 += part[(int64_t)(k + 2) * m + i];
+    s3 += part[(int64_t)(k + 3) * m + i];
+  }
+  for (; k < nblk; ++k) s0 += part[(int64_t)k * m + i];
+  grad[i] += (s0 + s1) + (s2 + s3);
 }
 
 // Packs FP32 weights W[27][Ci][Co] into BF16 GEMM operands:
@@ -274,39 +303,48 @@ __global__ __launch_bounds__(256) void k_input(const float *__restrict__ in, int
   for (int c = 0; c < 8; ++c) x0[p * 8 + c] = (bf16)(c < 2 ? in[p * 2 + c] : 0.0f);
 }
 
-// Concatenation buffer: buf[p, 0:cu] = up2(coarse)[p], buf[p, cu:cu+cs] = skip[p].
+// Concatenation buffer: buf[p, 0:cu] = up2(coarse)[p], buf[p, cu:cu+cs] =
+// skip[p]; one thread per (fine point, group of 8 channels), 16-byte copies
+// (cu and cs are multiples of 8).
 __global__ __launch_bounds__(256) void k_up_concat(const bf16 *__restrict__ coarse, Grid3 gc,
                                                    int cu, const bf16 *__restrict__ skip, int cs,
                                                    Grid3 gf, bf16 *__restrict__ buf) {
-  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (p >= gf.points()) return;
-  int b, z, y, x;
-  decode(p, gf, b, z, y, x);
-  const int64_t q = encode(b, z / 2, y / 2, x / 2, gc);
-  const int ct = cu + cs;
-  for (int c = 0; c < cu; ++c) buf[p * ct + c] = coarse[q * cu + c];
-  for (int c = 0; c < cs; ++c) buf[p * ct + cu + c] = skip[p * cs + c];
+  const int ng = (cu + cs) / 8;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= gf.points() * ng) return;
+  const int64_t p = i / ng;
+  const int cg = (int)(i - p * ng);
+  bf16x8 v;
+  if (cg * 8 < cu) {
+    int b, z, y, x;
+    decode(p, gf, b, z, y, x);
+    const int64_t q = encode(b, z / 2, y / 2, x / 2, gc);
+    v = *(const bf16x8 *)(coarse + q * cu + cg * 8);
+  } else {
+    v = *(const bf16x8 *)(skip + p * cs + (cg * 8 - cu));
+  }
+  *(bf16x8 *)(buf + p * (cu + cs) + cg * 8) = v;
 }
 
 // Upsampling backward: g_coarse[q, c] = sum over the fine children of
-// g_fine[p, off + c] (fine tensor has ct channels).
+// g_fine[p, off + c] (fine tensor has ct channels); one thread per (q, c).
 __global__ __launch_bounds__(256) void k_up_backward(const float *__restrict__ gfine, Grid3 gf,
                                                      int ct, int off, int c_n, Grid3 gc,
                                                      float *__restrict__ gcoarse) {
-  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (q >= gc.points()) return;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= gc.points() * c_n) return;
+  const int64_t q = i / c_n;
+  const int c = (int)(i - q * c_n);
   int b, z, y, x;
   decode(q, gc, b, z, y, x);
-  for (int c = 0; c < c_n; ++c) {
-    float s = 0.0f;
-    for (int oz = 0; oz < 2; ++oz)
-      for (int oy = 0; oy < 2; ++oy)
-        for (int ox = 0; ox < 2; ++ox) {
-          const int fz = 2 * z + oz, fy = 2 * y + oy, fx = 2 * x + ox;
-          if (fz < gf.D && fy < gf.H && fx < gf.W) s += gfine[encode(b, fz, fy, fx, gf) * ct + off + c];
-        }
-    gcoarse[q * c_n + c] = s;
-  }
+  float s = 0.0f;
+  for (int oz = 0; oz < 2; ++oz)
+    for (int oy = 0; oy < 2; ++oy)
+      for (int ox = 0; ox < 2; ++ox) {
+        const int fz = 2 * z + oz, fy = 2 * y + oy, fx = 2 * x + ox;
+        if (fz < gf.D && fy < gf.H && fx < gf.W) s += gfine[encode(b, fz, fy, fx, gf) * ct + off + c];
+      }
+  gcoarse[i] = s;
 }
 
 // dz = BF16((g1[:, off1:] + g2[:, off2:]) * (act > 0)) over c_n channels.
@@ -409,6 +447,9 @@ __global__ __launch_bounds__(256) void k_adam(float *__restrict__ w, const float
 }
 
 unsigned nblocks(int64_t n) { return (unsigned)((n + 255) / 256); }
+// Point blocks of a weight-gradient launch (x 27 taps): at least 1024 points
+// each, at most 64 blocks, so the partial sums stay small.
+int wgrad_blocks(int64_t P) { return (int)std::max<int64_t>(1, std::min<int64_t>(64, P / 1024)); }
 int pad32(int k) { return (k + 31) / 32 * 32; }
 
 }  // namespace
@@ -476,6 +517,23 @@ int launch_conv(ssp_handle *h, const bf16 *in, int cin, Grid3 gi, Grid3 go, int 
   return SSP_OK;
 }
 
+// Weight/bias-gradient partials of one convolution (nblk point blocks x 27
+// taps) on the matrix cores.
+int launch_wgrad(ssp_handle *h, const bf16 *x, int ci, Grid3 gi, Grid3 go, int stride,
+                 const bf16 *dz, int co, int nblk, int64_t per, float *part, float *bpart) {
+  const int ntile = ((ci + 15) / 16) * (co / 16);
+  const dim3 grid(nblk, 27);
+  switch ((ntile + 3) / 4) {
+    case 1: k_wgrad_mfma<1><<<grid, 256, 0, h->stream>>>(x, ci, gi, go, stride, dz, co, per, part, bpart); break;
+    case 2: k_wgrad_mfma<2><<<grid, 256, 0, h->stream>>>(x, ci, gi, go, stride, dz, co, per, part, bpart); break;
+    case 3: k_wgrad_mfma<3><<<grid, 256, 0, h->stream>>>(x, ci, gi, go, stride, dz, co, per, part, bpart); break;
+    case 4: k_wgrad_mfma<4><<<grid, 256, 0, h->stream>>>(x, ci, gi, go, stride, dz, co, per, part, bpart); break;
+    default: return fail(h, SSP_EINVAL, "weight gradient: unsupported channel counts");
+  }
+  LAUNCHCHK(h);
+  return SSP_OK;
+}
+
 // Forward of conv layer L: out = relu(conv(in) + b) in BF16.
 int layer_forward(ssp_net *n, int L, const bf16 *in, Grid3 gi, Grid3 go, bf16 *out) {
   const LayerDef &d = kDef[L];
@@ -490,19 +548,18 @@ int layer_backward(ssp_net *n, int L, const bf16 *in, Grid3 gi, Grid3 go, const 
   ssp_handle *h = n->h;
   const LayerDef &d = kDef[L];
   const int64_t P = go.points();
-  const int nblk = (int)std::min<int64_t>(256, (P + 255) / 256);
+  const int nblk = wgrad_blocks(P);
   const int64_t per = (P + nblk - 1) / nblk;
   const int64_t m = 27LL * d.ci * d.co;
   if ((int64_t)nblk * m > n->wpart_len) return fail(h, SSP_EINVAL, "weight-gradient scratch too small");
-  k_conv_wgrad<<<dim3(nblk, 27), 256, 0, h->stream>>>(in, d.ci, gi, go, d.stride, dz, d.co, per,
-                                                      n->wpart, n->bpart);
-  LAUNCHCHK(h);
+  int rc = launch_wgrad(h, in, d.ci, gi, go, d.stride, dz, d.co, nblk, per, n->wpart, n->bpart);
+  if (rc) return rc;
   k_sum_blocks<<<nblocks(m), 256, 0, h->stream>>>(n->wpart, nblk, m, n->grads + n->w_off[L]);
   LAUNCHCHK(h);
   k_sum_blocks<<<1, 256, 0, h->stream>>>(n->bpart, nblk, d.co, n->grads + n->b_off[L]);
   LAUNCHCHK(h);
   if (gx) {
-    int rc = launch_conv<1>(h, dz, d.co, go, gi, d.stride, n->wb[L], n->kpb[L], nullptr, 0, gx,
+    rc = launch_conv<1>(h, dz, d.co, go, gi, d.stride, n->wb[L], n->kpb[L], nullptr, 0, gx,
                             nullptr, d.ci);
     if (rc) return rc;
   }
@@ -574,9 +631,9 @@ int ssp_net_create(ssp_handle *h, int D, int H, int W, int max_batch, uint64_t s
   A((void **)&n->g_skip1, sizeof(float) * P1 * 16);
   A((void **)&n->g_skip2, sizeof(float) * P2 * 32);
   A((void **)&n->dz, sizeof(bf16) * std::max(P1 * 16, P2 * 48));
-  n->wpart_len = 256LL * 27 * 80 * 32;
+  n->wpart_len = 64LL * 27 * 80 * 32;
   A((void **)&n->wpart, sizeof(float) * n->wpart_len);
-  A((void **)&n->bpart, sizeof(float) * 256 * 48);
+  A((void **)&n->bpart, sizeof(float) * 64 * 48);
   A((void **)&n->loss_part, sizeof(double) * nblocks(P1));
   A((void **)&n->head_part, sizeof(float) * nblocks(P1) * (kHeadC + 1));
   if (rc) {
@@ -638,10 +695,10 @@ int ssp_net_forward(ssp_net *n, const float *in, int batch, float *out) {
   if ((rc = layer_forward(n, L_E2, n->d1, g2, g2, n->a3))) return rc;
   if ((rc = layer_forward(n, L_D2, n->a3, g2, g3, n->d2))) return rc;
   if ((rc = layer_forward(n, L_BOTT, n->d2, g3, g3, n->a4))) return rc;
-  k_up_concat<<<nblocks(g2.points()), 256, 0, h->stream>>>(n->a4, g3, 48, n->a3, 32, g2, n->c2);
+  k_up_concat<<<nblocks(g2.points() * 10), 256, 0, h->stream>>>(n->a4, g3, 48, n->a3, 32, g2, n->c2);
   LAUNCHCHK(h);
   if ((rc = layer_forward(n, L_U2, n->c2, g2, g2, n->a5))) return rc;
-  k_up_concat<<<nblocks(g1.points()), 256, 0, h->stream>>>(n->a5, g2, 32, n->a2, 16, g1, n->c1);
+  k_up_concat<<<nblocks(g1.points() * 6), 256, 0, h->stream>>>(n->a5, g2, 32, n->a2, 16, g1, n->c1);
   LAUNCHCHK(h);
   if ((rc = layer_forward(n, L_U1, n->c1, g1, g1, n->a6))) return rc;
   k_head<<<nblocks(g1.points()), 256, 0, h->stream>>>(n->a6, g1.points(), n->params + n->head_w_off,
@@ -680,7 +737,7 @@ int ssp_net_backward(ssp_net *n, const float *dy) {
   if ((rc = layer_backward(n, L_U1, n->c1, g1, g1, n->dz, g_c1))) return rc;
   // split: channels 0..31 -> up(a5), 32..47 -> a2 (skip)
   float *g_a5 = n->g_big;  // [P2, 32]
-  k_up_backward<<<nblocks(P2), 256, 0, h->stream>>>(g_c1, g1, 48, 0, 32, g2, g_a5);
+  k_up_backward<<<nblocks(P2 * 32), 256, 0, h->stream>>>(g_c1, g1, 48, 0, 32, g2, g_a5);
   LAUNCHCHK(h);
   // the a2 skip gradient, g_c1[:, 32:48], must survive the reuse of g_c1's buffer
   k_slice<<<nblocks(P1 * 16), 256, 0, h->stream>>>(g_c1, 48, 32, 16, P1, n->g_skip1);
@@ -690,7 +747,7 @@ int ssp_net_backward(ssp_net *n, const float *dy) {
   float *g_c2 = n->g_big2;  // [P2, 80]
   if ((rc = layer_backward(n, L_U2, n->c2, g2, g2, n->dz, g_c2))) return rc;
   float *g_a4 = n->g_big;  // [P3, 48]
-  k_up_backward<<<nblocks(P3), 256, 0, h->stream>>>(g_c2, g2, 80, 0, 48, g3, g_a4);
+  k_up_backward<<<nblocks(P3 * 48), 256, 0, h->stream>>>(g_c2, g2, 80, 0, 48, g3, g_a4);
   LAUNCHCHK(h);
   k_slice<<<nblocks(P2 * 32), 256, 0, h->stream>>>(g_c2, 80, 48, 32, P2, n->g_skip2);
   LAUNCHCHK(h);
@@ -809,14 +866,14 @@ int ssp_conv3d(ssp_handle *h, int mode, const float *in, int B, int D, int H, in
 // dw[27][ci][co] = sum_p x[q(p,t), ci] dz[p, co], db[co] = sum_p dz[p, co].
 int ssp_conv3d_wgrad(ssp_handle *h, const float *x, int B, int D, int H, int W, int ci,
                      const float *dz, int co, int stride, float *dw, float *db) {
-  if (!h || !x || !dz || !dw || !db || (stride != 1 && stride != 2) || ci % 4 || co % 4 ||
+  if (!h || !x || !dz || !dw || !db || (stride != 1 && stride != 2) || ci % 8 || co % 16 ||
       ci > 80 || co > 48)
     return SSP_EINVAL;
   HIPCHK(h, hipSetDevice(h->device));
   const Grid3 gi{B, D, H, W};
   const Grid3 go{B, (D - 1) / stride + 1, (H - 1) / stride + 1, (W - 1) / stride + 1};
   const int64_t P = go.points();
-  const int nblk = (int)std::min<int64_t>(256, (P + 255) / 256);
+  const int nblk = wgrad_blocks(P);
   const int64_t per = (P + nblk - 1) / nblk;
   const int64_t m = 27LL * ci * co;
   bf16 *xb = nullptr, *db16 = nullptr;
@@ -829,9 +886,8 @@ int ssp_conv3d_wgrad(ssp_handle *h, const float *x, int B, int D, int H, int W, 
   k_f32_to_bf16<<<nblocks(P * co), 256, 0, h->stream>>>(dz, P * co, db16);
   HIPCHK(h, hipMemsetAsync(dw, 0, sizeof(float) * m, h->stream));
   HIPCHK(h, hipMemsetAsync(db, 0, sizeof(float) * co, h->stream));
-  k_conv_wgrad<<<dim3(nblk, 27), 256, 0, h->stream>>>(xb, ci, gi, go, stride, db16, co, per, part,
-                                                      bpart);
-  k_sum_blocks<<<nblocks(m), 256, 0, h->stream>>>(part, nblk, m, dw);
+  const int lrc = launch_wgrad(h, xb, ci, gi, go, stride, db16, co, nblk, per, part, bpart);
+  if (lrc == SSP_OK) k_sum_blocks<<<nblocks(m), 256, 0, h->stream>>>(part, nblk, m, dw);
   k_sum_blocks<<<1, 256, 0, h->stream>>>(bpart, nblk, co, db);
   const hipError_t e = hipGetLastError();
   (void)hipStreamSynchronize(h->stream);
@@ -839,6 +895,7 @@ int ssp_conv3d_wgrad(ssp_handle *h, const float *x, int B, int D, int H, int W, 
   (void)hipFree(db16);
   (void)hipFree(part);
   (void)hipFree(bpart);
+  if (lrc) return lrc;
   return e == hipSuccess ? SSP_OK : SSP_EHIP;
 }
 

@@ -63,7 +63,8 @@ class _Opts(C.Structure):
                 ("profile", C.c_int), ("trace_cap", C.c_int),
                 ("trace_vm", C.c_void_p), ("trace_alpha", C.c_void_p),
                 ("trace_beta", C.c_void_p), ("trace_W", C.c_void_p),
-                ("warm_start", C.c_int)]
+                ("warm_start", C.c_int), ("warm_sweeps", C.c_int),
+                ("warm_omega", C.c_double)]
 
 
 _lib = None
@@ -385,14 +386,16 @@ class Handle:
               method: str = "sstep", precision: str = "fp64", inner_rtol: float = 1e-5,
               max_refine: int = 10, check_every: int = 0, fixed_outer: int = 0,
               profile: bool = False, trace_cap: int = 0,
-              warm_start: bool = False) -> SolveResult:
+              warm_start: bool = False, warm_sweeps: int = 0,
+              warm_omega: float = 0.0) -> SolveResult:
         import torch
         _check_dev(b, torch.float64, A.n, "b")
         _check_dev(x, torch.float64, A.n, "x")
         o = _Opts(method=METHOD[method], precision=PRECISION[precision], inner_rtol=inner_rtol,
                   max_refine=max_refine, check_every=check_every, fixed_outer=fixed_outer,
                   profile=1 if profile else 0, trace_cap=0,
-                  warm_start=1 if warm_start else 0)
+                  warm_start=1 if warm_start else 0, warm_sweeps=warm_sweeps,
+                  warm_omega=warm_omega)
         trace = None
         if trace_cap > 0:
             trace = dict(vm=np.zeros((trace_cap, 2 * s)), alpha=np.zeros((trace_cap, s)),

@@ -209,7 +209,8 @@ def test_adam_kernel(H):
     st = net.get_state()
     np.testing.assert_allclose(st[0], P["a"], rtol=0, atol=2e-6)
     np.testing.assert_allclose(st[1], M["a"], rtol=1e-5, atol=1e-7)
-    np.testing.assert_allclose(st[2], V["a"], rtol=1e-5, atol=1e-9)
+    # beta2 = 0.999 rounds to FP32 with a relative error of 1.3e-5 in 1 - beta2
+    np.testing.assert_allclose(st[2], V["a"], rtol=3e-5, atol=1e-9)
     net.close()
 
 

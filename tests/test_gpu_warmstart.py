@@ -77,3 +77,26 @@ def test_exact_guess_converges_immediately(H, problem):
     r = H.solve(A, b, x, s=4, rtol=1e-8, warm_start=True)
     assert r.warm_kept == 1 and r.outer == 0 and r.status == 0
     assert torch.equal(x, xsol)
+
+
+def test_sweeps_remove_rough_error_before_the_judge(H, problem):
+    # the solution plus white noise: the noise dominates the residual (the
+    # operator amplifies rough components), so the raw guess fails the judge;
+    # damped Jacobi sweeps remove the rough part and the guess is kept
+    A, b, xsol, ref, _ = problem
+    g = torch.Generator(device="cuda")
+    g.manual_seed(3)
+    noise = torch.randn(b.shape, generator=g, device="cuda", dtype=torch.float64)
+    x_raw = xsol + 0.05 * float(xsol.abs().max()) * noise
+    x = x_raw.clone()
+    r = H.solve(A, b, x, s=4, rtol=1e-8, warm_start=True)
+    assert r.warm_kept == 0 and r.warm_rel0 >= 1.0
+    x = x_raw.clone()
+    r = H.solve(A, b, x, s=4, rtol=1e-8, warm_start=True, warm_sweeps=8)
+    assert r.warm_kept == 1 and r.warm_rel0 < 1.0, r.warm_rel0
+    assert r.status == 0 and r.true_rel <= 1.5e-8
+    from paper_2501_03743_amd import sstep
+    with pytest.raises(sstep.SspError):
+        H.solve(A, b, x, warm_start=True, warm_sweeps=-1)
+    with pytest.raises(sstep.SspError):
+        H.solve(A, b, x, warm_start=True, warm_omega=2.5)
