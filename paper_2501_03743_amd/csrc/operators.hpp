@@ -64,21 +64,21 @@ __device__ __forceinline__ void csr_rows_staged(const CsrArgs<T> &A, const T *__
     const int e0 = A.rowptr[r0];
     const int cnt = A.rowptr[r1] - e0;
     if (cnt <= kCsrLds) {
+      // entries past the block's end re-read its last entry (cnt >= 1 here
+      // unless the block is empty, which stores nothing), so the loads and
+      // gathers need no branches and are all in flight together
       int ci[kPer];
       T vv[kPer];
+      const int last = cnt > 0 ? cnt - 1 : 0;
 #pragma unroll
       for (int u = 0; u < kPer; ++u) {
         const int e = threadIdx.x + u * kWG;
-        if (e < cnt) {
-          ci[u] = A.colind[e0 + e];
-          vv[u] = A.val[e0 + e];
-        }
+        const int ec = e < cnt ? e : last;
+        ci[u] = A.colind[e0 + ec];
+        vv[u] = A.val[e0 + ec];
       }
 #pragma unroll
-      for (int u = 0; u < kPer; ++u) {
-        const int e = threadIdx.x + u * kWG;
-        if (e < cnt) vv[u] = vv[u] * x[ci[u]];
-      }
+      for (int u = 0; u < kPer; ++u) vv[u] = vv[u] * x[ci[u]];
 #pragma unroll
       for (int u = 0; u < kPer; ++u) {
         const int e = threadIdx.x + u * kWG;
@@ -105,8 +105,11 @@ __device__ __forceinline__ void csr_rows_staged(const CsrArgs<T> &A, const T *__
   }
 }
 
-// Loads, gathers and sums one row in chunks of U stored entries (all loads of
-// a chunk are issued before any product is formed).
+// Loads, gathers and sums one row in chunks of U stored entries.  Every load
+// of a chunk is issued before any product is summed: entries past the row's
+// end re-read its last entry (a valid address, so no load needs a branch and
+// all of them are in flight together) and are left out of the sum, which
+// therefore has the same terms, order and rounding as a sequential product.
 template <typename T, int U>
 __device__ __forceinline__ T csr_row_sum(const CsrArgs<T> &A, const T *__restrict__ x, int a,
                                          int b) {
@@ -116,17 +119,18 @@ __device__ __forceinline__ T csr_row_sum(const CsrArgs<T> &A, const T *__restric
     int ci[U];
     T vv[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (e + u < b) {
-        ci[u] = A.colind[e + u];
-        vv[u] = A.val[e + u];
-      }
+    for (int u = 0; u < U; ++u) {
+      const int eu = (e + u < b) ? e + u : b - 1;
+      ci[u] = A.colind[eu];
+      vv[u] = A.val[eu];
+    }
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (e + u < b) vv[u] = vv[u] * x[ci[u]];
+    for (int u = 0; u < U; ++u) vv[u] = vv[u] * x[ci[u]];
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (e + u < b) acc += vv[u];
+    for (int u = 0; u < U; ++u) {
+      const T t = acc + vv[u];
+      acc = (e + u < b) ? t : acc;
+    }
   }
   return acc;
 }
@@ -199,54 +203,70 @@ __device__ __forceinline__ void stencil_rows(const StencilArgs<T> &S, const T *_
     const int xq = (int)rx, yq = (int)ry, z = (int)zq;
     T acc;
     if constexpr (KIND == K_3D27) {
-      T nb = 0;
-      for (int dz = -1; dz <= 1; ++dz) {
-        const int qz = z + dz;
-        if (qz < 0 || qz >= nz) continue;
-        for (int dy = -1; dy <= 1; ++dy) {
-          const int qy = yq + dy;
-          if (qy < 0 || qy >= ny) continue;
-          const T *row = x + (int64_t)qz * sz + (int64_t)qy * sy;
-          for (int dx = -1; dx <= 1; ++dx) {
-            const int qx = xq + dx;
-            if (qx < 0 || qx >= nx) continue;
-            if (dx == 0 && dy == 0 && dz == 0) continue;
-            nb += row[qx];
-          }
-        }
+      // all 26 neighbour loads first (out-of-grid ones re-read x[p]), then
+      // the sum over the neighbours inside the grid in definition order
+      T v[27];
+      bool in[27];
+#pragma unroll
+      for (int t = 0; t < 27; ++t) {
+        const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+        const bool ok = z + dz >= 0 && z + dz < nz && yq + dy >= 0 && yq + dy < ny &&
+                        xq + dx >= 0 && xq + dx < nx && t != 13;
+        in[t] = ok;
+        v[t] = x[ok ? p + dz * sz + dy * sy + dx : p];
       }
-      const T d = S.diag * x[p];
+      T nb = 0;
+#pragma unroll
+      for (int t = 0; t < 27; ++t) {
+        const T u = nb + v[t];
+        nb = in[t] ? u : nb;
+      }
+      const T d = S.diag * v[13];
       const T o = S.off * nb;
       acc = d + o;
     } else if constexpr (KIND == K_VARK) {
       const T kp = S.k[p];
       const bool in[6] = {z > 0, yq > 0, xq > 0, xq < nx - 1, yq < ny - 1, z < nz - 1};
       const int64_t q[6] = {p - sz, p - sy, p - 1, p + 1, p + sy, p + sz};
+      T kq[6], xv[6];
+#pragma unroll
+      for (int f6 = 0; f6 < 6; ++f6) {
+        const int64_t qq = in[f6] ? q[f6] : p;
+        kq[f6] = S.k[qq];
+        xv[f6] = x[qq];
+      }
+      const T xp = x[p];
       T dsum = 0, nb = 0;
 #pragma unroll
       for (int f6 = 0; f6 < 6; ++f6) {
-        if (in[f6]) {
-          const T w = face_weight(kp, S.k[q[f6]]);
-          dsum += w;
-          const T t = w * x[q[f6]];
-          nb += t;
-        } else {
-          dsum += kp;
-        }
+        const T w = face_weight(kp, kq[f6]);
+        const T t = w * xv[f6];
+        const T nb1 = nb + t;
+        const T ds1 = dsum + (in[f6] ? w : kp);
+        nb = in[f6] ? nb1 : nb;
+        dsum = ds1;
       }
-      const T d = dsum * x[p];
+      const T d = dsum * xp;
       acc = d - nb;
     } else {
-      T nb = 0;
-      if (xq > 0) nb += x[p - 1];
-      if (xq < nx - 1) nb += x[p + 1];
-      if (yq > 0) nb += x[p - sy];
-      if (yq < ny - 1) nb += x[p + sy];
+      const T xm = x[xq > 0 ? p - 1 : p], xpl = x[xq < nx - 1 ? p + 1 : p];
+      const T ym = x[yq > 0 ? p - sy : p], ypl = x[yq < ny - 1 ? p + sy : p];
+      T zm = 0, zpl = 0;
       if constexpr (KIND == K_3D7) {
-        if (z > 0) nb += x[p - sz];
-        if (z < nz - 1) nb += x[p + sz];
+        zm = x[z > 0 ? p - sz : p];
+        zpl = x[z < nz - 1 ? p + sz : p];
       }
-      const T d = S.diag * x[p];
+      const T xc = x[p];
+      T nb = 0;
+      nb = xq > 0 ? nb + xm : nb;
+      nb = xq < nx - 1 ? nb + xpl : nb;
+      nb = yq > 0 ? nb + ym : nb;
+      nb = yq < ny - 1 ? nb + ypl : nb;
+      if constexpr (KIND == K_3D7) {
+        nb = z > 0 ? nb + zm : nb;
+        nb = z < nz - 1 ? nb + zpl : nb;
+      }
+      const T d = S.diag * xc;
       const T o = S.off * nb;
       acc = d + o;
     }
