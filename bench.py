@@ -171,8 +171,8 @@ def bench_batch(H, seed=0, log=None):
     return out
 
 
-def bench_warmstart(H, n_train=2000, n_eval=200, side=96, epochs=12, lr=2e-3, batch=4,
-                    log=None):
+def bench_warmstart(H, n_train=2000, n_eval=200, side=96, epochs=24, lr=2e-3, batch=4,
+                    log=None, sweeps=16):
     """The learned warm start on -div(k grad u) = f at side^3: log k a Gaussian
     random field (sigma 1, correlation length 0.1), f a random sum of 16
     Fourier modes; the network trained on n_train solver solutions (seeds
@@ -193,7 +193,7 @@ def bench_warmstart(H, n_train=2000, n_eval=200, side=96, epochs=12, lr=2e-3, ba
     del data
     torch.cuda.empty_cache()
     seeds = list(range(20000, 20000 + n_eval))
-    rec = ws.evaluate(H, model, seeds, s=S, rtol=RTOL)
+    rec = ws.evaluate(H, model, seeds, s=S, rtol=RTOL, sweeps=sweeps)
     summ = ws.summarize(rec)
     # the full forms at equal final accuracy on the first held-out seeds
     forms = {}
@@ -214,7 +214,8 @@ def bench_warmstart(H, n_train=2000, n_eval=200, side=96, epochs=12, lr=2e-3, ba
             t1 = time.perf_counter()
             if warm:
                 model.predict(logk, f, out=x)
-            r = H.solve(A, b, x, s=S, rtol=RTOL, maxit=MAXIT, warm_start=warm, **kw)
+            r = H.solve(A, b, x, s=S, rtol=RTOL, maxit=MAXIT, warm_start=warm,
+                        warm_sweeps=sweeps if warm else 0, **kw)
             torch.cuda.synchronize()
             ts.append(time.perf_counter() - t1)
             its.append(r.cg_equiv if kw.get("method") != "pcg" else r.outer)
@@ -228,6 +229,7 @@ def bench_warmstart(H, n_train=2000, n_eval=200, side=96, epochs=12, lr=2e-3, ba
         "workload": "-div(k grad u)=f on %d^3, log k GRF (sigma 1, l 0.1), f = 16 Fourier modes, "
                     "s=4, rtol 1e-8" % side,
         "train_samples": n_train, "eval_samples": n_eval, "epochs": len(hist),
+        "loss": "energy e^T (L + 1e-3 I) e", "smoothing_sweeps": sweeps,
         "generate_s": gen_s, "train_s": train_s, "loss_first": hist[0], "loss_last": hist[-1],
         "params": params,
         "held_out": summ, "forms_first_%d" % m: forms,
@@ -251,7 +253,7 @@ def main():
     ap.add_argument("--ws-train", type=int, default=2000)
     ap.add_argument("--ws-eval", type=int, default=200)
     ap.add_argument("--ws-side", type=int, default=96)
-    ap.add_argument("--ws-epochs", type=int, default=12)
+    ap.add_argument("--ws-epochs", type=int, default=24)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only a plain 1 GiB device-to-device copy, three times (the "
                          "reference for the FETCH_SIZE / WRITE_SIZE counter scale)")

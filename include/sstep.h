@@ -260,12 +260,14 @@ int ssp_autotune_batch(ssp_handle *h, int nsys, const ssp_matrix *const *A,
  * (log k, f) of a variable-coefficient Poisson problem on a D x H x W grid
  * to an initial guess x0 (the learned-warm-start extension).  Convolutions
  * run on the BF16 matrix cores with FP32 accumulation; master weights, Adam
- * moments and gradients are FP32.  Layers: 3x3x3 convolutions
- * 8->16, 16->16, 16->32 (stride 2), 32->32, 32->48 (stride 2), 48->48,
- * 80->32 (after nearest upsampling and concatenation with the 32-channel
- * level), 48->16 (likewise with the 16-channel level), then a 1x1 head
- * 16->1; ReLU after every 3x3x3 convolution; zero padding of one cell.
- * Weights are He-normal from `seed`, biases zero. */
+ * moments and gradients are FP32.  The levels are 4x apart (two stride-2
+ * convolutions down, nearest upsampling by 4 up), so the coarsest level's
+ * receptive field covers the grid.  Layers: 3x3x3 convolutions 8->16,
+ * 16->16 | 16->16 /2, 16->32 /2 | 32->32 | 32->32 /2, 32->48 /2 | 48->32 |
+ * 64->32 (after upsampling and concatenation with the 32-channel level),
+ * 48->16 (likewise with the 16-channel level), then a 1x1 head 16->1; ReLU
+ * after every 3x3x3 convolution; zero padding of one cell.  Weights are
+ * He-normal from `seed`, biases zero. */
 typedef struct ssp_net ssp_net;
 
 int ssp_net_create(ssp_handle *h, int D, int H, int W, int max_batch, uint64_t seed,
@@ -286,6 +288,15 @@ int ssp_net_forward(ssp_net *net, const float *in, int batch, float *out);
  * FP32, batch*D*H*W): writes dy = 2 (y - t) / N (DEVICE) and, if loss is a
  * HOST pointer, the mean squared error (synchronises). */
 int ssp_net_loss(ssp_net *net, const float *y, const float *target, float *dy, double *loss);
+
+/* Energy-type loss of the last forward's output y against target (DEVICE,
+ * FP32, [batch][D][H][W]): with e = y - target and L the 7-point Laplacian
+ * of each sample's grid (zero outside it), loss = e^T (L + lambda I) e / N
+ * and dy = 2 (L e + lambda e) / N, N = batch * D * H * W.  It weighs the
+ * error as CG started from y does (energy norm of a constant-coefficient
+ * operator), rather than by its mean square.  lambda >= 0. */
+int ssp_net_loss_h1(ssp_net *net, const float *y, const float *target, float lambda, float *dy,
+                    double *loss);
 
 /* Accumulates the parameter gradients of the last forward for the output
  * gradient dy (DEVICE FP32); ssp_net_zero_grad clears them. */

@@ -6,22 +6,28 @@ zero padding of one cell; stride-2 convolutions sample every other output.
 Tensors are channels-last [B, D, H, W, C].  Weights are [27, Ci, Co] with tap
 t = (dz+1)*9 + (dy+1)*3 + (dx+1).
 
-The network (a 3-level U-shaped conv net) is:
-  a1 = relu(conv(x, 8->16))        a2 = relu(conv(a1, 16->16))
-  d1 = relu(conv_s2(a2, 16->32))   a3 = relu(conv(d1, 32->32))
-  d2 = relu(conv_s2(a3, 32->48))   a4 = relu(conv(d2, 48->48))
-  c2 = [up2(a4), a3]               a5 = relu(conv(c2, 80->32))
-  c1 = [up2(a5), a2]               a6 = relu(conv(c1, 48->16))
-  y  = a6 . w_head + b_head        (1x1 head, 16 -> 1)
-(input channels: log k and f, zero-padded to 8.)
+The network (a 3-level U-shaped conv net; each level is 4x coarser than the
+one above it, reached by two stride-2 convolutions, so the coarsest level
+sees the whole domain) is:
+  a1 = relu(conv(x, 8->16))          a2 = relu(conv(a1, 16->16))       level 1
+  h1 = relu(conv_s2(a2, 16->16))     d1 = relu(conv_s2(h1, 16->32))
+  a3 = relu(conv(d1, 32->32))                                          level 2
+  h2 = relu(conv_s2(a3, 32->32))     d2 = relu(conv_s2(h2, 32->48))
+  a4 = relu(conv(d2, 48->32))                                          level 3
+  c2 = [up4(a4), a3]                 a5 = relu(conv(c2, 64->32))       level 2
+  c1 = [up4(a5), a2]                 a6 = relu(conv(c1, 48->16))       level 1
+  y  = a6 . w_head + b_head          (1x1 head, 16 -> 1)
+(input channels: log k and f, zero-padded to 8; up4 = nearest-neighbour
+upsampling by 4, cropped to the finer grid.)
 """
 from __future__ import annotations
 
 import numpy as np
 
 LAYERS = [  # name, Ci, Co, stride
-    ("e1a", 8, 16, 1), ("e1b", 16, 16, 1), ("d1", 16, 32, 2), ("e2", 32, 32, 1),
-    ("d2", 32, 48, 2), ("bott", 48, 48, 1), ("u2", 80, 32, 1), ("u1", 48, 16, 1),
+    ("e1a", 8, 16, 1), ("e1b", 16, 16, 1), ("d1a", 16, 16, 2), ("d1b", 16, 32, 2),
+    ("e2", 32, 32, 1), ("d2a", 32, 32, 2), ("d2b", 32, 48, 2), ("bott", 48, 32, 1),
+    ("u2", 64, 32, 1), ("u1", 48, 16, 1),
 ]
 HEAD_C = 16
 
@@ -66,21 +72,21 @@ def conv3d_backward(x, w, dy, stride=1):
     return dxp[:, 1:-1, 1:-1, 1:-1], dw, db
 
 
-def up2(x, shape):
-    """Nearest-neighbour upsampling by 2, cropped to the spatial shape."""
+def upsample(x, shape, f):
+    """Nearest-neighbour upsampling by f, cropped to the spatial shape."""
     D, H, W = shape
-    y = x.repeat(2, axis=1).repeat(2, axis=2).repeat(2, axis=3)
+    y = x.repeat(f, axis=1).repeat(f, axis=2).repeat(f, axis=3)
     return y[:, :D, :H, :W]
 
 
-def up2_backward(dy, coarse_shape):
+def upsample_backward(dy, coarse_shape, f):
     B, D, H, W, C = dy.shape
     d, h, w = coarse_shape
     out = np.zeros((B, d, h, w, C))
-    for oz in range(2):
-        for oy in range(2):
-            for ox in range(2):
-                part = dy[:, oz::2, oy::2, ox::2]
+    for oz in range(f):
+        for oy in range(f):
+            for ox in range(f):
+                part = dy[:, oz::f, oy::f, ox::f]
                 out[:, :part.shape[1], :part.shape[2], :part.shape[3]] += part
     return out
 
@@ -107,14 +113,16 @@ def forward(P, x):
     shape1 = x.shape[1:4]
     c["a1"] = relu(conv3d(x, P["e1a.w"], P["e1a.b"]))
     c["a2"] = relu(conv3d(c["a1"], P["e1b.w"], P["e1b.b"]))
-    c["d1"] = relu(conv3d(c["a2"], P["d1.w"], P["d1.b"], 2))
+    c["h1"] = relu(conv3d(c["a2"], P["d1a.w"], P["d1a.b"], 2))
+    c["d1"] = relu(conv3d(c["h1"], P["d1b.w"], P["d1b.b"], 2))
     c["a3"] = relu(conv3d(c["d1"], P["e2.w"], P["e2.b"]))
-    c["d2"] = relu(conv3d(c["a3"], P["d2.w"], P["d2.b"], 2))
+    c["h2"] = relu(conv3d(c["a3"], P["d2a.w"], P["d2a.b"], 2))
+    c["d2"] = relu(conv3d(c["h2"], P["d2b.w"], P["d2b.b"], 2))
     c["a4"] = relu(conv3d(c["d2"], P["bott.w"], P["bott.b"]))
     shape2 = c["a3"].shape[1:4]
-    c["c2"] = np.concatenate([up2(c["a4"], shape2), c["a3"]], axis=-1)
+    c["c2"] = np.concatenate([upsample(c["a4"], shape2, 4), c["a3"]], axis=-1)
     c["a5"] = relu(conv3d(c["c2"], P["u2.w"], P["u2.b"]))
-    c["c1"] = np.concatenate([up2(c["a5"], shape1), c["a2"]], axis=-1)
+    c["c1"] = np.concatenate([upsample(c["a5"], shape1, 4), c["a2"]], axis=-1)
     c["a6"] = relu(conv3d(c["c1"], P["u1.w"], P["u1.b"]))
     y = c["a6"] @ P["head.w"] + P["head.b"][0]
     return y, c
@@ -129,22 +137,26 @@ def backward(P, c, dy):
     dz = da6 * (c["a6"] > 0)
     dc1, G["u1.w"], G["u1.b"] = conv3d_backward(c["c1"], P["u1.w"], dz)
     c_up = c["a5"].shape[-1]
-    da5 = up2_backward(dc1[..., :c_up], c["a5"].shape[1:4])
+    da5 = upsample_backward(dc1[..., :c_up], c["a5"].shape[1:4], 4)
     da2 = dc1[..., c_up:]
     dz = da5 * (c["a5"] > 0)
     dc2, G["u2.w"], G["u2.b"] = conv3d_backward(c["c2"], P["u2.w"], dz)
     c_up = c["a4"].shape[-1]
-    da4 = up2_backward(dc2[..., :c_up], c["a4"].shape[1:4])
+    da4 = upsample_backward(dc2[..., :c_up], c["a4"].shape[1:4], 4)
     da3 = dc2[..., c_up:]
     dz = da4 * (c["a4"] > 0)
     dd2, G["bott.w"], G["bott.b"] = conv3d_backward(c["d2"], P["bott.w"], dz)
     dz = dd2 * (c["d2"] > 0)
-    da3b, G["d2.w"], G["d2.b"] = conv3d_backward(c["a3"], P["d2.w"], dz, 2)
+    dh2, G["d2b.w"], G["d2b.b"] = conv3d_backward(c["h2"], P["d2b.w"], dz, 2)
+    dz = dh2 * (c["h2"] > 0)
+    da3b, G["d2a.w"], G["d2a.b"] = conv3d_backward(c["a3"], P["d2a.w"], dz, 2)
     da3 = da3 + da3b
     dz = da3 * (c["a3"] > 0)
     dd1, G["e2.w"], G["e2.b"] = conv3d_backward(c["d1"], P["e2.w"], dz)
     dz = dd1 * (c["d1"] > 0)
-    da2b, G["d1.w"], G["d1.b"] = conv3d_backward(c["a2"], P["d1.w"], dz, 2)
+    dh1, G["d1b.w"], G["d1b.b"] = conv3d_backward(c["h1"], P["d1b.w"], dz, 2)
+    dz = dh1 * (c["h1"] > 0)
+    da2b, G["d1a.w"], G["d1a.b"] = conv3d_backward(c["a2"], P["d1a.w"], dz, 2)
     da2 = da2 + da2b
     dz = da2 * (c["a2"] > 0)
     da1, G["e1b.w"], G["e1b.b"] = conv3d_backward(c["a1"], P["e1b.w"], dz)
@@ -157,6 +169,27 @@ def mse(y, t):
     """Mean squared error and its gradient."""
     d = y - t
     return float(np.mean(d * d)), 2.0 * d / d.size
+
+
+def laplacian7(e):
+    """(L e) for the 7-point Laplacian on each sample's grid, zero outside:
+    6 e_p minus the in-grid neighbours."""
+    out = 6.0 * e
+    out[:, 1:] -= e[:, :-1]
+    out[:, :-1] -= e[:, 1:]
+    out[:, :, 1:] -= e[:, :, :-1]
+    out[:, :, :-1] -= e[:, :, 1:]
+    out[:, :, :, 1:] -= e[:, :, :, :-1]
+    out[:, :, :, :-1] -= e[:, :, :, 1:]
+    return out
+
+
+def h1_loss(y, t, lam):
+    """Energy-type loss e^T (L + lam I) e / N of e = y - t ([B, D, H, W]) and
+    its gradient 2 (L e + lam e) / N."""
+    e = y - t
+    le = laplacian7(e) + lam * e
+    return float(np.sum(e * le)) / e.size, 2.0 * le / e.size
 
 
 def adam(P, G, M, V, step, lr, b1=0.9, b2=0.999, eps=1e-8):

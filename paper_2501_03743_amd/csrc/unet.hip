@@ -11,9 +11,12 @@
 //     head, the squared-error loss and Adam, as streaming kernels.
 //
 // Tensors are channels-last [B, D, H, W, C]; activations are BF16, gradients
-// FP32, master weights and Adam moments FP32.  Layer table (Ci -> Co, stride):
-//   e1a 8->16, e1b 16->16, d1 16->32 /2, e2 32->32, d2 32->48 /2, bott 48->48,
-//   u2 80->32 (up(bott) ++ e2), u1 48->16 (up(u2) ++ e1b), head 16->1.
+// FP32, master weights and Adam moments FP32.  Layer table (Ci -> Co, stride);
+// the three levels are 4x apart, so the coarsest sees the whole domain:
+//   level 1: e1a 8->16, e1b 16->16;  down: d1a 16->16 /2, d1b 16->32 /2
+//   level 2: e2 32->32;              down: d2a 32->32 /2, d2b 32->48 /2
+//   level 3: bott 48->32
+//   up: u2 64->32 (up4(bott) ++ e2), u1 48->16 (up4(u2) ++ e1b), head 16->1.
 #include <cstdint>
 #include <cstring>
 #include <random>
@@ -29,14 +32,16 @@ namespace {
 
 using namespace ssp;
 
-constexpr int kLayers = 8;
+constexpr int kLayers = 10;
 constexpr int kHeadC = 16;
 struct LayerDef {
   int ci, co, stride;
 };
-constexpr LayerDef kDef[kLayers] = {{8, 16, 1},  {16, 16, 1}, {16, 32, 2}, {32, 32, 1},
-                                    {32, 48, 2}, {48, 48, 1}, {80, 32, 1}, {48, 16, 1}};
-enum { L_E1A, L_E1B, L_D1, L_E2, L_D2, L_BOTT, L_U2, L_U1 };
+constexpr LayerDef kDef[kLayers] = {{8, 16, 1},  {16, 16, 1}, {16, 16, 2}, {16, 32, 2},
+                                    {32, 32, 1}, {32, 32, 2}, {32, 48, 2}, {48, 32, 1},
+                                    {64, 32, 1}, {48, 16, 1}};
+enum { L_E1A, L_E1B, L_D1A, L_D1B, L_E2, L_D2A, L_D2B, L_BOTT, L_U2, L_U1 };
+constexpr int kUp = 4;   // levels are 4x apart (two stride-2 convolutions down)
 
 struct Grid3 {
   int B, D, H, W;
@@ -303,12 +308,12 @@ __global__ __launch_bounds__(256) void k_input(const float *__restrict__ in, int
   for (int c = 0; c < 8; ++c) x0[p * 8 + c] = (bf16)(c < 2 ? in[p * 2 + c] : 0.0f);
 }
 
-// Concatenation buffer: buf[p, 0:cu] = up2(coarse)[p], buf[p, cu:cu+cs] =
-// skip[p]; one thread per (fine point, group of 8 channels), 16-byte copies
-// (cu and cs are multiples of 8).
+// Concatenation buffer: buf[p, 0:cu] = up_f(coarse)[p] (nearest neighbour,
+// factor f), buf[p, cu:cu+cs] = skip[p]; one thread per (fine point, group
+// of 8 channels), 16-byte copies (cu and cs are multiples of 8).
 __global__ __launch_bounds__(256) void k_up_concat(const bf16 *__restrict__ coarse, Grid3 gc,
                                                    int cu, const bf16 *__restrict__ skip, int cs,
-                                                   Grid3 gf, bf16 *__restrict__ buf) {
+                                                   Grid3 gf, int f, bf16 *__restrict__ buf) {
   const int ng = (cu + cs) / 8;
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= gf.points() * ng) return;
@@ -318,7 +323,7 @@ __global__ __launch_bounds__(256) void k_up_concat(const bf16 *__restrict__ coar
   if (cg * 8 < cu) {
     int b, z, y, x;
     decode(p, gf, b, z, y, x);
-    const int64_t q = encode(b, z / 2, y / 2, x / 2, gc);
+    const int64_t q = encode(b, z / f, y / f, x / f, gc);
     v = *(const bf16x8 *)(coarse + q * cu + cg * 8);
   } else {
     v = *(const bf16x8 *)(skip + p * cs + (cg * 8 - cu));
@@ -326,10 +331,10 @@ __global__ __launch_bounds__(256) void k_up_concat(const bf16 *__restrict__ coar
   *(bf16x8 *)(buf + p * (cu + cs) + cg * 8) = v;
 }
 
-// Upsampling backward: g_coarse[q, c] = sum over the fine children of
+// Upsampling backward: g_coarse[q, c] = sum over the f^3 fine children of
 // g_fine[p, off + c] (fine tensor has ct channels); one thread per (q, c).
 __global__ __launch_bounds__(256) void k_up_backward(const float *__restrict__ gfine, Grid3 gf,
-                                                     int ct, int off, int c_n, Grid3 gc,
+                                                     int ct, int off, int c_n, Grid3 gc, int f,
                                                      float *__restrict__ gcoarse) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= gc.points() * c_n) return;
@@ -338,10 +343,10 @@ __global__ __launch_bounds__(256) void k_up_backward(const float *__restrict__ g
   int b, z, y, x;
   decode(q, gc, b, z, y, x);
   float s = 0.0f;
-  for (int oz = 0; oz < 2; ++oz)
-    for (int oy = 0; oy < 2; ++oy)
-      for (int ox = 0; ox < 2; ++ox) {
-        const int fz = 2 * z + oz, fy = 2 * y + oy, fx = 2 * x + ox;
+  for (int oz = 0; oz < f; ++oz)
+    for (int oy = 0; oy < f; ++oy)
+      for (int ox = 0; ox < f; ++ox) {
+        const int fz = f * z + oz, fy = f * y + oy, fx = f * x + ox;
         if (fz < gf.D && fy < gf.H && fx < gf.W) s += gfine[encode(b, fz, fy, fx, gf) * ct + off + c];
       }
   gcoarse[i] = s;
@@ -431,6 +436,44 @@ __global__ __launch_bounds__(256) void k_mse(const float *__restrict__ y, const 
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
+// Energy-type loss of the error e = y - t on each sample's grid:
+// per point l_p = e_p (L e)_p + lambda e_p^2 with L the 7-point Laplacian
+// (6 e_p minus the in-grid neighbours; zero outside), so that sum_p l_p =
+// e^T (L + lambda I) e; dy = 2 (L e + lambda e) / N, and per-block partial
+// sums of l_p.  Penalising the error's gradients matches what CG started
+// from y pays for: its energy norm, not its mean square.
+__global__ __launch_bounds__(256) void k_loss_h1(const float *__restrict__ y,
+                                                 const float *__restrict__ t, Grid3 g, float lam,
+                                                 float *__restrict__ dy, double *__restrict__ part) {
+  __shared__ double red[256];
+  const int64_t N = g.points();
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double l = 0.0;
+  if (p < N) {
+    int b, z, yy, x;
+    decode(p, g, b, z, yy, x);
+    const int64_t sy = g.W, sz = (int64_t)g.W * g.H;
+    const float ep = y[p] - t[p];
+    float nb = 0.0f;
+    if (x > 0) nb += y[p - 1] - t[p - 1];
+    if (x < g.W - 1) nb += y[p + 1] - t[p + 1];
+    if (yy > 0) nb += y[p - sy] - t[p - sy];
+    if (yy < g.H - 1) nb += y[p + sy] - t[p + sy];
+    if (z > 0) nb += y[p - sz] - t[p - sz];
+    if (z < g.D - 1) nb += y[p + sz] - t[p + sz];
+    const float le = 6.0f * ep - nb;
+    dy[p] = 2.0f * (le + lam * ep) / (float)N;
+    l = (double)ep * ((double)le + (double)lam * (double)ep);
+  }
+  red[threadIdx.x] = l;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
 // Adam with bias correction (Kingma & Ba), FP32 master parameters.
 __global__ __launch_bounds__(256) void k_adam(float *__restrict__ w, const float *__restrict__ g,
                                               float *__restrict__ m, float *__restrict__ v,
@@ -467,8 +510,9 @@ struct ssp_net {
   bf16 *wf[kLayers] = {}, *wb[kLayers] = {};
   int kpf[kLayers], kpb[kLayers];
   // activations (BF16)
-  bf16 *x0 = nullptr, *a1 = nullptr, *a2 = nullptr, *d1 = nullptr, *a3 = nullptr, *d2 = nullptr,
-       *a4 = nullptr, *c2 = nullptr, *a5 = nullptr, *c1 = nullptr, *a6 = nullptr;
+  bf16 *x0 = nullptr, *a1 = nullptr, *a2 = nullptr, *h1 = nullptr, *d1 = nullptr, *a3 = nullptr,
+       *h2 = nullptr, *d2 = nullptr, *a4 = nullptr, *c2 = nullptr, *a5 = nullptr, *c1 = nullptr,
+       *a6 = nullptr;
   // backward scratch
   float *g_big = nullptr, *g_big2 = nullptr, *g_skip1 = nullptr, *g_skip2 = nullptr;
   bf16 *dz = nullptr;
@@ -510,6 +554,7 @@ int launch_conv(ssp_handle *h, const bf16 *in, int cin, Grid3 gi, Grid3 go, int 
     case 1: k_conv_mfma<MODE, 1><<<grid, 256, 0, h->stream>>>(in, cin, gi, go, stride, wt, kp, bias, relu, out_f, out_b); break;
     case 2: k_conv_mfma<MODE, 2><<<grid, 256, 0, h->stream>>>(in, cin, gi, go, stride, wt, kp, bias, relu, out_f, out_b); break;
     case 3: k_conv_mfma<MODE, 3><<<grid, 256, 0, h->stream>>>(in, cin, gi, go, stride, wt, kp, bias, relu, out_f, out_b); break;
+    case 4: k_conv_mfma<MODE, 4><<<grid, 256, 0, h->stream>>>(in, cin, gi, go, stride, wt, kp, bias, relu, out_f, out_b); break;
     case 5: k_conv_mfma<MODE, 5><<<grid, 256, 0, h->stream>>>(in, cin, gi, go, stride, wt, kp, bias, relu, out_f, out_b); break;
     default: return fail(h, SSP_EINVAL, "conv: unsupported channel count");
   }
@@ -599,9 +644,9 @@ int ssp_net_create(ssp_handle *h, int D, int H, int W, int max_batch, uint64_t s
   n->head_b_off = off;
   off += 1;
   n->nparam = off;
-  const Grid3 g1 = grid_level(n, 0, max_batch), g2 = grid_level(n, 1, max_batch),
-              g3 = grid_level(n, 2, max_batch);
-  const int64_t P1 = g1.points(), P2 = g2.points(), P3 = g3.points();
+  // grids: g0 full, g1 = /2, g2 = /4 (level 2), g3 = /8, g4 = /16 (level 3)
+  int64_t P[5];
+  for (int l = 0; l < 5; ++l) P[l] = grid_level(n, l, max_batch).points();
   int rc = SSP_OK;
   auto A = [&](void **p, size_t bytes) {
     if (rc == SSP_OK) rc = net_alloc(n, p, bytes);
@@ -614,28 +659,30 @@ int ssp_net_create(ssp_handle *h, int D, int H, int W, int max_batch, uint64_t s
     A((void **)&n->wf[L], sizeof(bf16) * kDef[L].co * n->kpf[L]);
     A((void **)&n->wb[L], sizeof(bf16) * kDef[L].ci * n->kpb[L]);
   }
-  A((void **)&n->x0, sizeof(bf16) * P1 * 8);
-  A((void **)&n->a1, sizeof(bf16) * P1 * 16);
-  A((void **)&n->a2, sizeof(bf16) * P1 * 16);
-  A((void **)&n->d1, sizeof(bf16) * P2 * 32);
-  A((void **)&n->a3, sizeof(bf16) * P2 * 32);
-  A((void **)&n->d2, sizeof(bf16) * P3 * 48);
-  A((void **)&n->a4, sizeof(bf16) * P3 * 48);
-  A((void **)&n->c2, sizeof(bf16) * P2 * 80);
-  A((void **)&n->a5, sizeof(bf16) * P2 * 32);
-  A((void **)&n->c1, sizeof(bf16) * P1 * 48);
-  A((void **)&n->a6, sizeof(bf16) * P1 * 16);
-  const int64_t big = std::max(P1 * 48, P2 * 80);
+  A((void **)&n->x0, sizeof(bf16) * P[0] * 8);
+  A((void **)&n->a1, sizeof(bf16) * P[0] * 16);
+  A((void **)&n->a2, sizeof(bf16) * P[0] * 16);
+  A((void **)&n->h1, sizeof(bf16) * P[1] * 16);
+  A((void **)&n->d1, sizeof(bf16) * P[2] * 32);
+  A((void **)&n->a3, sizeof(bf16) * P[2] * 32);
+  A((void **)&n->h2, sizeof(bf16) * P[3] * 32);
+  A((void **)&n->d2, sizeof(bf16) * P[4] * 48);
+  A((void **)&n->a4, sizeof(bf16) * P[4] * 32);
+  A((void **)&n->c2, sizeof(bf16) * P[2] * 64);
+  A((void **)&n->a5, sizeof(bf16) * P[2] * 32);
+  A((void **)&n->c1, sizeof(bf16) * P[0] * 48);
+  A((void **)&n->a6, sizeof(bf16) * P[0] * 16);
+  const int64_t big = std::max({P[0] * 48, P[1] * 16, P[2] * 64, P[3] * 32, P[4] * 48});
   A((void **)&n->g_big, sizeof(float) * big);
   A((void **)&n->g_big2, sizeof(float) * big);
-  A((void **)&n->g_skip1, sizeof(float) * P1 * 16);
-  A((void **)&n->g_skip2, sizeof(float) * P2 * 32);
-  A((void **)&n->dz, sizeof(bf16) * std::max(P1 * 16, P2 * 48));
+  A((void **)&n->g_skip1, sizeof(float) * P[0] * 16);
+  A((void **)&n->g_skip2, sizeof(float) * P[2] * 32);
+  A((void **)&n->dz, sizeof(bf16) * std::max({P[0] * 16, P[1] * 16, P[2] * 32, P[3] * 32, P[4] * 48}));
   n->wpart_len = 64LL * 27 * 80 * 32;
   A((void **)&n->wpart, sizeof(float) * n->wpart_len);
   A((void **)&n->bpart, sizeof(float) * 64 * 48);
-  A((void **)&n->loss_part, sizeof(double) * nblocks(P1));
-  A((void **)&n->head_part, sizeof(float) * nblocks(P1) * (kHeadC + 1));
+  A((void **)&n->loss_part, sizeof(double) * nblocks(P[0]));
+  A((void **)&n->head_part, sizeof(float) * nblocks(P[0]) * (kHeadC + 1));
   if (rc) {
     ssp_net_destroy(n);
     return fail(h, rc, "ssp_net_create: allocation failed");
@@ -685,24 +732,29 @@ int ssp_net_forward(ssp_net *n, const float *in, int batch, float *out) {
         n->params + n->w_off[L], kDef[L].ci, kDef[L].co, n->wf[L], n->kpf[L], n->wb[L], n->kpb[L]);
     LAUNCHCHK(h);
   }
-  const Grid3 g1 = grid_level(n, 0, batch), g2 = grid_level(n, 1, batch), g3 = grid_level(n, 2, batch);
-  k_input<<<nblocks(g1.points()), 256, 0, h->stream>>>(in, g1.points(), n->x0);
+  Grid3 g[5];
+  for (int l = 0; l < 5; ++l) g[l] = grid_level(n, l, batch);
+  k_input<<<nblocks(g[0].points()), 256, 0, h->stream>>>(in, g[0].points(), n->x0);
   LAUNCHCHK(h);
   int rc;
-  if ((rc = layer_forward(n, L_E1A, n->x0, g1, g1, n->a1))) return rc;
-  if ((rc = layer_forward(n, L_E1B, n->a1, g1, g1, n->a2))) return rc;
-  if ((rc = layer_forward(n, L_D1, n->a2, g1, g2, n->d1))) return rc;
-  if ((rc = layer_forward(n, L_E2, n->d1, g2, g2, n->a3))) return rc;
-  if ((rc = layer_forward(n, L_D2, n->a3, g2, g3, n->d2))) return rc;
-  if ((rc = layer_forward(n, L_BOTT, n->d2, g3, g3, n->a4))) return rc;
-  k_up_concat<<<nblocks(g2.points() * 10), 256, 0, h->stream>>>(n->a4, g3, 48, n->a3, 32, g2, n->c2);
+  if ((rc = layer_forward(n, L_E1A, n->x0, g[0], g[0], n->a1))) return rc;
+  if ((rc = layer_forward(n, L_E1B, n->a1, g[0], g[0], n->a2))) return rc;
+  if ((rc = layer_forward(n, L_D1A, n->a2, g[0], g[1], n->h1))) return rc;
+  if ((rc = layer_forward(n, L_D1B, n->h1, g[1], g[2], n->d1))) return rc;
+  if ((rc = layer_forward(n, L_E2, n->d1, g[2], g[2], n->a3))) return rc;
+  if ((rc = layer_forward(n, L_D2A, n->a3, g[2], g[3], n->h2))) return rc;
+  if ((rc = layer_forward(n, L_D2B, n->h2, g[3], g[4], n->d2))) return rc;
+  if ((rc = layer_forward(n, L_BOTT, n->d2, g[4], g[4], n->a4))) return rc;
+  k_up_concat<<<nblocks(g[2].points() * 8), 256, 0, h->stream>>>(n->a4, g[4], 32, n->a3, 32, g[2],
+                                                                 kUp, n->c2);
   LAUNCHCHK(h);
-  if ((rc = layer_forward(n, L_U2, n->c2, g2, g2, n->a5))) return rc;
-  k_up_concat<<<nblocks(g1.points() * 6), 256, 0, h->stream>>>(n->a5, g2, 32, n->a2, 16, g1, n->c1);
+  if ((rc = layer_forward(n, L_U2, n->c2, g[2], g[2], n->a5))) return rc;
+  k_up_concat<<<nblocks(g[0].points() * 6), 256, 0, h->stream>>>(n->a5, g[2], 32, n->a2, 16, g[0],
+                                                                 kUp, n->c1);
   LAUNCHCHK(h);
-  if ((rc = layer_forward(n, L_U1, n->c1, g1, g1, n->a6))) return rc;
-  k_head<<<nblocks(g1.points()), 256, 0, h->stream>>>(n->a6, g1.points(), n->params + n->head_w_off,
-                                                     n->params + n->head_b_off, out);
+  if ((rc = layer_forward(n, L_U1, n->c1, g[0], g[0], n->a6))) return rc;
+  k_head<<<nblocks(g[0].points()), 256, 0, h->stream>>>(n->a6, g[0].points(), n->params + n->head_w_off,
+                                                        n->params + n->head_b_off, out);
   LAUNCHCHK(h);
   n->batch = batch;
   return SSP_OK;
@@ -719,70 +771,70 @@ int ssp_net_backward(ssp_net *n, const float *dy) {
   ssp_handle *h = n->h;
   HIPCHK(h, hipSetDevice(h->device));
   const int batch = n->batch;
-  const Grid3 g1 = grid_level(n, 0, batch), g2 = grid_level(n, 1, batch), g3 = grid_level(n, 2, batch);
-  const int64_t P1 = g1.points(), P2 = g2.points(), P3 = g3.points();
+  Grid3 g[5];
+  int64_t P[5];
+  for (int l = 0; l < 5; ++l) {
+    g[l] = grid_level(n, l, batch);
+    P[l] = g[l].points();
+  }
+  float *A = n->g_big, *B = n->g_big2;   // ping-pong FP32 gradient buffers
   int rc;
+  auto relu_grad = [&](int64_t Pn, int c, const float *g1, const float *g2, const bf16 *act) {
+    k_relu_grad<<<nblocks(Pn * c), 256, 0, h->stream>>>(Pn, c, g1, c, 0, g2, c, 0, act, n->dz);
+    return hipGetLastError() == hipSuccess ? SSP_OK : fail(h, SSP_EHIP, "kernel launch failed");
+  };
   // head
-  float *g_a6 = n->g_big;  // [P1, 16]
-  k_head_backward<<<nblocks(P1), 256, 0, h->stream>>>(n->a6, P1, n->params + n->head_w_off, dy,
-                                                      g_a6, n->head_part);
+  k_head_backward<<<nblocks(P[0]), 256, 0, h->stream>>>(n->a6, P[0], n->params + n->head_w_off, dy,
+                                                        A, n->head_part);
   LAUNCHCHK(h);
-  k_sum_blocks<<<1, 256, 0, h->stream>>>(n->head_part, (int)nblocks(P1), kHeadC + 1,
+  k_sum_blocks<<<1, 256, 0, h->stream>>>(n->head_part, (int)nblocks(P[0]), kHeadC + 1,
                                          n->grads + n->head_w_off);
   LAUNCHCHK(h);
-  // u1: in c1 [P1, 48] -> a6
-  k_relu_grad<<<nblocks(P1 * 16), 256, 0, h->stream>>>(P1, 16, g_a6, 16, 0, nullptr, 0, 0, n->a6, n->dz);
+  // u1: c1 = [up4(a5), a2] (48 channels) -> a6
+  if ((rc = relu_grad(P[0], 16, A, nullptr, n->a6))) return rc;
+  if ((rc = layer_backward(n, L_U1, n->c1, g[0], g[0], n->dz, B))) return rc;
+  k_up_backward<<<nblocks(P[2] * 32), 256, 0, h->stream>>>(B, g[0], 48, 0, 32, g[2], kUp, A);
   LAUNCHCHK(h);
-  float *g_c1 = n->g_big2;  // [P1, 48]
-  if ((rc = layer_backward(n, L_U1, n->c1, g1, g1, n->dz, g_c1))) return rc;
-  // split: channels 0..31 -> up(a5), 32..47 -> a2 (skip)
-  float *g_a5 = n->g_big;  // [P2, 32]
-  k_up_backward<<<nblocks(P2 * 32), 256, 0, h->stream>>>(g_c1, g1, 48, 0, 32, g2, g_a5);
+  // the a2 skip gradient, channels 32..47, must survive the reuse of B
+  k_slice<<<nblocks(P[0] * 16), 256, 0, h->stream>>>(B, 48, 32, 16, P[0], n->g_skip1);
   LAUNCHCHK(h);
-  // the a2 skip gradient, g_c1[:, 32:48], must survive the reuse of g_c1's buffer
-  k_slice<<<nblocks(P1 * 16), 256, 0, h->stream>>>(g_c1, 48, 32, 16, P1, n->g_skip1);
+  // u2: c2 = [up4(a4), a3] (64 channels) -> a5
+  if ((rc = relu_grad(P[2], 32, A, nullptr, n->a5))) return rc;
+  if ((rc = layer_backward(n, L_U2, n->c2, g[2], g[2], n->dz, B))) return rc;
+  k_up_backward<<<nblocks(P[4] * 32), 256, 0, h->stream>>>(B, g[2], 64, 0, 32, g[4], kUp, A);
   LAUNCHCHK(h);
-  k_relu_grad<<<nblocks(P2 * 32), 256, 0, h->stream>>>(P2, 32, g_a5, 32, 0, nullptr, 0, 0, n->a5, n->dz);
+  k_slice<<<nblocks(P[2] * 32), 256, 0, h->stream>>>(B, 64, 32, 32, P[2], n->g_skip2);
   LAUNCHCHK(h);
-  float *g_c2 = n->g_big2;  // [P2, 80]
-  if ((rc = layer_backward(n, L_U2, n->c2, g2, g2, n->dz, g_c2))) return rc;
-  float *g_a4 = n->g_big;  // [P3, 48]
-  k_up_backward<<<nblocks(P3 * 48), 256, 0, h->stream>>>(g_c2, g2, 80, 0, 48, g3, g_a4);
-  LAUNCHCHK(h);
-  k_slice<<<nblocks(P2 * 32), 256, 0, h->stream>>>(g_c2, 80, 48, 32, P2, n->g_skip2);
-  LAUNCHCHK(h);
-  k_relu_grad<<<nblocks(P3 * 48), 256, 0, h->stream>>>(P3, 48, g_a4, 48, 0, nullptr, 0, 0, n->a4, n->dz);
-  LAUNCHCHK(h);
-  float *g_d2 = n->g_big2;  // [P3, 48]
-  if ((rc = layer_backward(n, L_BOTT, n->d2, g3, g3, n->dz, g_d2))) return rc;
-  k_relu_grad<<<nblocks(P3 * 48), 256, 0, h->stream>>>(P3, 48, g_d2, 48, 0, nullptr, 0, 0, n->d2, n->dz);
-  LAUNCHCHK(h);
-  float *g_a3b = n->g_big;  // [P2, 32]
-  if ((rc = layer_backward(n, L_D2, n->a3, g2, g3, n->dz, g_a3b))) return rc;
-  k_relu_grad<<<nblocks(P2 * 32), 256, 0, h->stream>>>(P2, 32, g_a3b, 32, 0, n->g_skip2, 32, 0, n->a3, n->dz);
-  LAUNCHCHK(h);
-  float *g_d1 = n->g_big2;  // [P2, 32]
-  if ((rc = layer_backward(n, L_E2, n->d1, g2, g2, n->dz, g_d1))) return rc;
-  k_relu_grad<<<nblocks(P2 * 32), 256, 0, h->stream>>>(P2, 32, g_d1, 32, 0, nullptr, 0, 0, n->d1, n->dz);
-  LAUNCHCHK(h);
-  float *g_a2b = n->g_big;  // [P1, 16]
-  if ((rc = layer_backward(n, L_D1, n->a2, g1, g2, n->dz, g_a2b))) return rc;
-  k_relu_grad<<<nblocks(P1 * 16), 256, 0, h->stream>>>(P1, 16, g_a2b, 16, 0, n->g_skip1, 16, 0, n->a2, n->dz);
-  LAUNCHCHK(h);
-  float *g_a1 = n->g_big2;  // [P1, 16]
-  if ((rc = layer_backward(n, L_E1B, n->a1, g1, g1, n->dz, g_a1))) return rc;
-  k_relu_grad<<<nblocks(P1 * 16), 256, 0, h->stream>>>(P1, 16, g_a1, 16, 0, nullptr, 0, 0, n->a1, n->dz);
-  LAUNCHCHK(h);
-  if ((rc = layer_backward(n, L_E1A, n->x0, g1, g1, n->dz, nullptr))) return rc;
+  // bott: d2 -> a4
+  if ((rc = relu_grad(P[4], 32, A, nullptr, n->a4))) return rc;
+  if ((rc = layer_backward(n, L_BOTT, n->d2, g[4], g[4], n->dz, B))) return rc;
+  // d2b: h2 -> d2 (stride 2)
+  if ((rc = relu_grad(P[4], 48, B, nullptr, n->d2))) return rc;
+  if ((rc = layer_backward(n, L_D2B, n->h2, g[3], g[4], n->dz, A))) return rc;
+  // d2a: a3 -> h2 (stride 2)
+  if ((rc = relu_grad(P[3], 32, A, nullptr, n->h2))) return rc;
+  if ((rc = layer_backward(n, L_D2A, n->a3, g[2], g[3], n->dz, B))) return rc;
+  // e2: d1 -> a3 (a3 also feeds the u2 skip)
+  if ((rc = relu_grad(P[2], 32, B, n->g_skip2, n->a3))) return rc;
+  if ((rc = layer_backward(n, L_E2, n->d1, g[2], g[2], n->dz, A))) return rc;
+  // d1b: h1 -> d1 (stride 2)
+  if ((rc = relu_grad(P[2], 32, A, nullptr, n->d1))) return rc;
+  if ((rc = layer_backward(n, L_D1B, n->h1, g[1], g[2], n->dz, B))) return rc;
+  // d1a: a2 -> h1 (stride 2)
+  if ((rc = relu_grad(P[1], 16, B, nullptr, n->h1))) return rc;
+  if ((rc = layer_backward(n, L_D1A, n->a2, g[0], g[1], n->dz, A))) return rc;
+  // e1b: a1 -> a2 (a2 also feeds the u1 skip)
+  if ((rc = relu_grad(P[0], 16, A, n->g_skip1, n->a2))) return rc;
+  if ((rc = layer_backward(n, L_E1B, n->a1, g[0], g[0], n->dz, B))) return rc;
+  // e1a: x0 -> a1
+  if ((rc = relu_grad(P[0], 16, B, nullptr, n->a1))) return rc;
+  if ((rc = layer_backward(n, L_E1A, n->x0, g[0], g[0], n->dz, nullptr))) return rc;
   return SSP_OK;
 }
 
-int ssp_net_loss(ssp_net *n, const float *y, const float *target, float *dy, double *loss) {
-  if (!n || !y || !target || !dy || n->batch < 1) return SSP_EINVAL;
+namespace {
+int finish_loss(ssp_net *n, unsigned nb, int64_t N, double *loss) {
   ssp_handle *h = n->h;
-  const int64_t N = grid_level(n, 0, n->batch).points();
-  const unsigned nb = nblocks(N);
-  k_mse<<<nb, 256, 0, h->stream>>>(y, target, N, dy, n->loss_part);
   LAUNCHCHK(h);
   if (loss) {
     std::vector<double> part(nb);
@@ -794,6 +846,25 @@ int ssp_net_loss(ssp_net *n, const float *y, const float *target, float *dy, dou
     *loss = s / (double)N;
   }
   return SSP_OK;
+}
+}  // namespace
+
+int ssp_net_loss(ssp_net *n, const float *y, const float *target, float *dy, double *loss) {
+  if (!n || !y || !target || !dy || n->batch < 1) return SSP_EINVAL;
+  const int64_t N = grid_level(n, 0, n->batch).points();
+  const unsigned nb = nblocks(N);
+  k_mse<<<nb, 256, 0, n->h->stream>>>(y, target, N, dy, n->loss_part);
+  return finish_loss(n, nb, N, loss);
+}
+
+int ssp_net_loss_h1(ssp_net *n, const float *y, const float *target, float lambda, float *dy,
+                    double *loss) {
+  if (!n || !y || !target || !dy || n->batch < 1 || !(lambda >= 0.0f)) return SSP_EINVAL;
+  const Grid3 g = grid_level(n, 0, n->batch);
+  const int64_t N = g.points();
+  const unsigned nb = nblocks(N);
+  k_loss_h1<<<nb, 256, 0, n->h->stream>>>(y, target, g, lambda, dy, n->loss_part);
+  return finish_loss(n, nb, N, loss);
 }
 
 int ssp_net_adam_step(ssp_net *n, float lr, float beta1, float beta2, float eps, int step) {

@@ -39,6 +39,7 @@ EXPORTS = (
     "ssp_net_forward", "ssp_net_zero_grad", "ssp_net_backward", "ssp_net_loss",
     "ssp_net_adam_step", "ssp_net_get_state", "ssp_net_set_state", "ssp_conv3d",
     "ssp_conv3d_wgrad", "ssp_net_mfma_selftest", "ssp_get_warm_start",
+    "ssp_net_loss_h1",
 )
 
 
@@ -118,6 +119,7 @@ def load():
         "ssp_net_zero_grad": (i32, [vp]),
         "ssp_net_backward": (i32, [vp, vp]),
         "ssp_net_loss": (i32, [vp, vp, vp, vp, C.POINTER(dbl)]),
+        "ssp_net_loss_h1": (i32, [vp, vp, vp, C.c_float, vp, C.POINTER(dbl)]),
         "ssp_net_adam_step": (i32, [vp, C.c_float, C.c_float, C.c_float, C.c_float, i32]),
         "ssp_net_get_state": (i32, [vp, vp, i64]),
         "ssp_net_set_state": (i32, [vp, vp, i64]),
@@ -556,6 +558,18 @@ class Net:
         v = C.c_double()
         self._rc(load().ssp_net_loss(self._p, _ptr(y), _ptr(target), _ptr(dy), C.byref(v)),
                  "ssp_net_loss")
+        return v.value, dy
+
+    def loss_h1(self, y, target, lam, dy=None):
+        """Energy-type loss e^T (L + lam I) e / N (L: 7-point Laplacian); returns (loss, dy)."""
+        import torch
+        if dy is None:
+            dy = torch.empty_like(y)
+        _check_dev(y, torch.float32, name="y")
+        _check_dev(target, torch.float32, y.numel(), "target")
+        v = C.c_double()
+        self._rc(load().ssp_net_loss_h1(self._p, _ptr(y), _ptr(target), float(lam), _ptr(dy),
+                                        C.byref(v)), "ssp_net_loss_h1")
         return v.value, dy
 
     def zero_grad(self):

@@ -166,6 +166,17 @@ def test_net_forward_backward_against_oracle(H):
     net.close()
 
 
+def test_h1_loss_kernel(H):
+    inp, tgt = _case(5, (2, 9, 7, 6))
+    net = H.net(inp.shape[1:4], max_batch=2, seed=3)
+    y = net.forward(torch.from_numpy(inp).cuda())
+    loss, dy = net.loss_h1(y, torch.from_numpy(tgt).cuda(), 0.05)
+    lo, dyo = U.h1_loss(y.cpu().numpy().astype(np.float64), tgt.astype(np.float64), 0.05)
+    assert abs(loss - lo) <= 1e-5 * abs(lo)
+    np.testing.assert_allclose(dy.cpu().numpy(), dyo, rtol=1e-4, atol=1e-6 * np.abs(dyo).max())
+    net.close()
+
+
 def test_net_deterministic_and_state_roundtrip(H):
     inp, tgt = _case(2, (1, 9, 8, 11))
     inp_d, tgt_d = torch.from_numpy(inp).cuda(), torch.from_numpy(tgt).cuda()

@@ -100,3 +100,25 @@ def test_sweeps_remove_rough_error_before_the_judge(H, problem):
         H.solve(A, b, x, warm_start=True, warm_sweeps=-1)
     with pytest.raises(sstep.SspError):
         H.solve(A, b, x, warm_start=True, warm_omega=2.5)
+
+
+def test_learned_warm_start_gain(H):
+    # A small instance of the whole method: solver-generated training data,
+    # the network trained by the library's kernels, held-out seeds solved from
+    # x0 = 0 and from the network's (smoothed, judged) guess.  The gain is
+    # statistical: the assertion is on the mean over the held-out seeds, and
+    # against the same smoothing applied to x0 = 0 as well, so that the
+    # network itself must contribute.
+    from paper_2501_03743_amd import warmstart as ws
+    shape = (32, 32, 32)
+    data = ws.generate(H, shape, list(range(10000, 10256)))
+    model = ws.WarmStart(H, shape, batch=4, seed=0)
+    hist = model.fit(data, 30, lr=2e-3)
+    assert hist[-1] < 0.5 * hist[0]
+    rec = ws.evaluate(H, model, list(range(20000, 20024)), sweeps=16)
+    summ = ws.summarize(rec)
+    print("warm start 32^3:", summ)
+    model.close()
+    assert summ["true_rel_max_warm"] <= 1.5e-8 and summ["true_rel_max_zero"] <= 1.5e-8
+    assert summ["iteration_gain"] > 0.05, summ
+    assert summ["outer_warm_mean"] < summ["outer_smoothed_zero_mean"], summ

@@ -99,17 +99,24 @@ def test_conv_backward_adjoint(stride, shape):
     np.testing.assert_allclose(db, dy.sum(axis=(0, 1, 2, 3)), rtol=1e-12)
 
 
-@pytest.mark.parametrize("fine", [(4, 4, 4), (5, 6, 7)])
-def test_up2_adjoint(fine):
+@pytest.mark.parametrize("f,fine", [(2, (4, 4, 4)), (2, (5, 6, 7)), (4, (9, 6, 13)), (4, (4, 4, 4))])
+def test_upsample_adjoint(f, fine):
     g = np.random.default_rng(4)
-    coarse = tuple((n - 1) // 2 + 1 for n in fine)
+    coarse = tuple((n - 1) // f + 1 for n in fine)
     a = g.standard_normal((2,) + coarse + (3,))
-    u = U.up2(a, fine)
+    u = U.upsample(a, fine, f)
     assert u.shape == (2,) + fine + (3,)
-    # nearest neighbour: u[z, y, x] = a[z // 2, y // 2, x // 2]
-    assert u[1, fine[0] - 1, 1, fine[2] - 1, 2] == a[1, (fine[0] - 1) // 2, 0, (fine[2] - 1) // 2, 2]
+    # nearest neighbour: u[z, y, x] = a[z // f, y // f, x // f]
+    for z, y, x in ((fine[0] - 1, 1, fine[2] - 1), (0, fine[1] - 1, 2)):
+        np.testing.assert_array_equal(u[1, z, y, x], a[1, z // f, y // f, x // f])
     d = g.standard_normal(u.shape)
-    assert abs(np.sum(u * d) - np.sum(a * U.up2_backward(d, coarse))) < 1e-11
+    assert abs(np.sum(u * d) - np.sum(a * U.upsample_backward(d, coarse, f))) < 1e-11
+
+
+def test_two_halvings_match_a_quarter():
+    # the level-2 grid of two stride-2 convolutions is the up4 coarse grid
+    for n in range(1, 40):
+        assert U.out_size(U.out_size(n, 2), 2) == (n - 1) // 4 + 1
 
 
 def test_net_backward_finite_differences():
@@ -158,6 +165,33 @@ def test_mse_gradient():
         yp[i] += e
         ym[i] -= e
         assert abs((U.mse(yp, t)[0] - U.mse(ym, t)[0]) / (2 * e) - d[i]) < 1e-8
+
+
+def test_h1_loss_sine_mode_and_gradient():
+    # a Dirichlet sine mode is an eigenvector of the 7-point Laplacian with
+    # eigenvalue sum_d (2 - 2 cos(pi k_d h_d)), h_d = 1 / (n_d + 1)
+    D, H, W = 7, 6, 9
+    kz, ky, kx = 2, 1, 3
+    z = np.arange(1, D + 1)[:, None, None] / (D + 1)
+    y = np.arange(1, H + 1)[None, :, None] / (H + 1)
+    x = np.arange(1, W + 1)[None, None, :] / (W + 1)
+    v = np.sin(np.pi * kz * z) * np.sin(np.pi * ky * y) * np.sin(np.pi * kx * x)
+    lam = sum(2 - 2 * np.cos(np.pi * k / (n + 1)) for k, n in ((kz, D), (ky, H), (kx, W)))
+    e = v[None]
+    np.testing.assert_allclose(U.laplacian7(e), lam * e, atol=1e-12)
+    L, _ = U.h1_loss(e, np.zeros_like(e), 0.25)
+    assert abs(L - (lam + 0.25) * np.sum(v * v) / v.size) < 1e-12
+    g = np.random.default_rng(8)
+    yy, tt = g.standard_normal((2, 4, 5, 3)), g.standard_normal((2, 4, 5, 3))
+    L, d = U.h1_loss(yy, tt, 0.1)
+    assert L > 0
+    h = 1e-6
+    for idx in ((0, 0, 0, 0), (1, 2, 3, 1), (0, 3, 4, 2)):
+        yp, ym = yy.copy(), yy.copy()
+        yp[idx] += h
+        ym[idx] -= h
+        fd = (U.h1_loss(yp, tt, 0.1)[0] - U.h1_loss(ym, tt, 0.1)[0]) / (2 * h)
+        assert abs(fd - d[idx]) < 1e-7
 
 
 def test_adam_first_step_is_signed_lr():
