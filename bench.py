@@ -103,16 +103,15 @@ def cpu_baseline(gpu_outer, budget_s=20.0):
                       "scaled to the %d outer iterations of the full solve" % (k2, S, per, gpu_outer)}
 
 
-def bench_batch(H, seed=0, log=None):
-    """32 variable-coefficient 7-point systems, sides L ~ U{32..160}, k =
+def bench_batch(H, count=32, lo=32, hi=160, seed=0):
+    """`count` variable-coefficient 7-point systems, sides L ~ U{lo..hi}, k =
     exp(g) with g a Gaussian random field (sigma 0.5, correlation length 0.1),
-    b ~ N(0, 1): one persistent launch (autotuned tiles and schedule) against
-    the same systems solved one after another, all to rtol 1e-8 with FP32
-    matrix powers and FP64 moments, s x s solves and refinement."""
+    b ~ N(0, 1): one batched solve (autotuned schedule, tiles and grid)
+    against the same systems solved one after another, all to rtol 1e-8 with
+    FP32 matrix powers and FP64 moments, s x s solves and refinement."""
     import torch
-    from paper_2501_03743_amd import sstep
     from paper_2501_03743_amd import workloads as wl
-    sides = [int(v) for v in wl.batch_sides(seed)]
+    sides = [int(v) for v in wl.batch_sides(seed, count, lo, hi)]
     mats, bs, keep = [], [], []
     for i, L in enumerate(sides):
         shape = (L, L, L)
@@ -139,6 +138,17 @@ def bench_batch(H, seed=0, log=None):
     reps = [batch_once() for _ in range(3)]
     t_batch = min(r[0] for r in reps)
     _, st, it, tr = reps[-1]
+    persistent = None
+    if tune.schedule != 0:
+        from paper_2501_03743_amd import sstep
+        tp = sstep.Tune(tile_rows=tune.tile_rows, grid=1024, order=1, schedule=0)
+        for v in xs:
+            v.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        H.solve_batch(mats, bs, xs, s=S, rtol=RTOL, maxit=MAXIT, tune=tp)
+        torch.cuda.synchronize()
+        persistent = time.perf_counter() - t0
 
     def seq_once(precision):
         res = []
@@ -154,11 +164,13 @@ def bench_batch(H, seed=0, log=None):
     t_seq, res_seq = min((seq_once("mixed_ir") for _ in range(2)), key=lambda r: r[0])
     t_seq64, res64 = seq_once("fp64")
     out = {
-        "workload": "32 x 3D 7-point variable-coefficient Poisson, L ~ U{32..160} (sum n = %d), "
-                    "k = exp(GRF sigma 0.5, l 0.1), b ~ N(0,1), s=4, rtol 1e-8" % sum(L ** 3 for L in sides),
+        "workload": "%d x 3D 7-point variable-coefficient Poisson, L ~ U{%d..%d} (sum n = %d), "
+                    "k = exp(GRF sigma 0.5, l 0.1), b ~ N(0,1), s=4, rtol 1e-8"
+                    % (count, lo, hi, sum(L ** 3 for L in sides)),
         "sides": sides,
         "tune": tune.as_dict(), "autotune_s": tune_s,
-        "batch_one_launch_s": t_batch,
+        "batch_s": t_batch,
+        "persistent_launch_s": persistent,
         "sequential_mixed_s": t_seq,
         "sequential_fp64_s": t_seq64,
         "speedup_vs_sequential_mixed": t_seq / t_batch,
@@ -411,7 +423,10 @@ def main():
         A2.close()
         del b2, x2, xref
 
-    config3 = bench_batch(H) if args.batch else None
+    config3 = None
+    if args.batch:
+        config3 = {"batch32_L32_160": bench_batch(H),
+                   "batch128_L12_40": bench_batch(H, count=128, lo=12, hi=40, seed=1)}
 
     out = {
         "metric": "time-to-solution @rtol 1e-8 (s) + SpMV/matrix-powers HBM GB/s, s-step vs CG",

@@ -226,6 +226,11 @@ typedef struct ssp_tune {
                           first; 1 = round-robin start per workgroup          */
   int spin_limit;      /* consecutive empty polls without global progress
                           after which the launch gives up (default 2^20)      */
+  int schedule;        /* 0 = one persistent launch (workgroups claim tiles);
+                          1 = stepped: one launch pair per phase step of all
+                          systems together (no in-kernel synchronisation;
+                          grid, order and spin_limit unused).  Both give the
+                          same results bit for bit                             */
 } ssp_tune;
 
 /* Solves nsys independent systems A[i] x[i] = b[i] in ONE persistent launch
@@ -246,8 +251,8 @@ int ssp_solve_batch(ssp_handle *h, int nsys, const ssp_matrix *const *A,
                     int maxit, const ssp_opts *opts, const ssp_tune *tune,
                     int *status_out, int *outer_out, double *true_rel_out);
 
-/* Chooses tile size, grid size and scan order for a batch by timing short
- * runs of ssp_solve_batch on scratch iterates; with a non-NULL cache_path the
+/* Chooses the schedule, tile size, grid size and scan order for a batch by
+ * timing short runs of ssp_solve_batch on scratch iterates; with a non-NULL cache_path the
  * choice is read from / appended to that text file, keyed by architecture,
  * batch size, total rows (log2), s and operator kinds. */
 int ssp_autotune_batch(ssp_handle *h, int nsys, const ssp_matrix *const *A,

@@ -32,6 +32,20 @@ struct BatchTable {
 };
 using BT = BatchTable<1, 2, 3, 4, 5, 6, 7, 8>;
 
+template <int... Ss>
+struct StepTable {
+  static int launch(int s, int ntiles, int nsys, hipStream_t st, const BatchSys *sys,
+                    BatchSched *sched, BatchGlobal *glob, const int *tsys, const int *tidx) {
+    int done = 0;
+    ((s == Ss ? (k_batch_tiles<Ss><<<ntiles, kWG, 0, st>>>(sys, sched, tsys, tidx),
+                 k_batch_step<Ss><<<nsys, kWG, 0, st>>>(sys, sched, glob), done = 1, 0)
+              : 0),
+     ...);
+    return done;
+  }
+};
+using ST = StepTable<1, 2, 3, 4, 5, 6, 7, 8>;
+
 struct Layout {
   int64_t n, ld, tile_rows;
   int ntiles;
@@ -66,6 +80,8 @@ int ssp_solve_batch(ssp_handle *h, int nsys, const ssp_matrix *const *A, const d
   const int order = tune ? tune->order : 0;
   const unsigned spin = (tune && tune->spin_limit > 0) ? (unsigned)tune->spin_limit : kDefaultSpin;
   const int64_t trq = tune ? tune->tile_rows : 0;
+  const int schedule = tune ? tune->schedule : 0;
+  if (schedule != 0 && schedule != 1) return fail(h, SSP_EINVAL, "ssp_solve_batch: bad schedule");
 
   // layout of the per-system arrays in one device buffer
   std::vector<Layout> L(nsys);
@@ -104,6 +120,14 @@ int ssp_solve_batch(ssp_handle *h, int nsys, const ssp_matrix *const *A, const d
   bytes = align256(bytes + sizeof(BatchGlobal));
   const size_t off_order = bytes;
   bytes = align256(bytes + sizeof(int) * nsys);
+  int64_t total_tiles = 0;
+  for (int i = 0; i < nsys; ++i) total_tiles += L[i].ntiles;
+  if (schedule == 1 && total_tiles > (int64_t)INT32_MAX / 2)
+    return fail(h, SSP_EINVAL, "ssp_solve_batch: too many tiles for the stepped schedule");
+  const size_t off_tsys = bytes;
+  bytes = align256(bytes + (schedule == 1 ? sizeof(int) * total_tiles : 0));
+  const size_t off_tidx = bytes;
+  bytes = align256(bytes + (schedule == 1 ? sizeof(int) * total_tiles : 0));
   if (bytes > h->batch_bytes) {
     if (h->batch_mem) (void)hipFree(h->batch_mem);
     h->batch_mem = nullptr;
@@ -179,11 +203,49 @@ int ssp_solve_batch(ssp_handle *h, int nsys, const ssp_matrix *const *A, const d
   HIPCHK(h, hipMemcpyAsync(base + off_glob, &g, sizeof(g), hipMemcpyHostToDevice, h->stream));
   HIPCHK(h, hipMemcpyAsync(base + off_order, ord.data(), sizeof(int) * nsys,
                            hipMemcpyHostToDevice, h->stream));
-  if (!BT::launch(s, grid, h->stream, (const BatchSys *)(base + off_sys),
-                  (BatchSched *)(base + off_sched), (BatchGlobal *)(base + off_glob), nsys,
-                  (const int *)(base + off_order), order, spin))
-    return fail(h, SSP_EINVAL, "ssp_solve_batch: no kernel for s");
-  LAUNCHCHK(h);
+  if (schedule == 0) {
+    if (!BT::launch(s, grid, h->stream, (const BatchSys *)(base + off_sys),
+                    (BatchSched *)(base + off_sched), (BatchGlobal *)(base + off_glob), nsys,
+                    (const int *)(base + off_order), order, spin))
+      return fail(h, SSP_EINVAL, "ssp_solve_batch: no kernel for s");
+    LAUNCHCHK(h);
+  } else {
+    // work-item map (largest systems first), then launch pairs until every
+    // system is done; the host reads the done counter every few steps
+    std::vector<int> tsys, tidx;
+    tsys.reserve(total_tiles);
+    tidx.reserve(total_tiles);
+    std::vector<int> big(nsys);
+    for (int i = 0; i < nsys; ++i) big[i] = i;
+    std::stable_sort(big.begin(), big.end(), [&](int a, int c) { return L[a].n > L[c].n; });
+    for (int i : big)
+      for (int t = 0; t < L[i].ntiles; ++t) {
+        tsys.push_back(i);
+        tidx.push_back(t);
+      }
+    HIPCHK(h, hipMemcpyAsync(base + off_tsys, tsys.data(), sizeof(int) * total_tiles,
+                             hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(base + off_tidx, tidx.data(), sizeof(int) * total_tiles,
+                             hipMemcpyHostToDevice, h->stream));
+    // a system needs at most (max_refine + 1) * (2 + inner_max * (s + 1)) steps
+    const int64_t max_steps = (int64_t)(max_refine + 1) * (2 + (int64_t)inner_max * (s + 1)) + 1;
+    const int every = 8;
+    BatchGlobal gp;
+    for (int64_t step = 0;;) {
+      for (int q = 0; q < every; ++q, ++step)
+        if (!ST::launch(s, (int)total_tiles, nsys, h->stream, (const BatchSys *)(base + off_sys),
+                        (BatchSched *)(base + off_sched), (BatchGlobal *)(base + off_glob),
+                        (const int *)(base + off_tsys), (const int *)(base + off_tidx)))
+          return fail(h, SSP_EINVAL, "ssp_solve_batch: no kernel for s");
+      LAUNCHCHK(h);
+      HIPCHK(h, hipMemcpyAsync(&gp, base + off_glob, sizeof(gp), hipMemcpyDeviceToHost,
+                               h->stream));
+      HIPCHK(h, hipStreamSynchronize(h->stream));
+      if (gp.ndone >= (unsigned)nsys) break;
+      if (step > max_steps)
+        return fail(h, SSP_EHIP, "ssp_solve_batch: stepped schedule exceeded its step bound");
+    }
+  }
   HIPCHK(h, hipMemcpyAsync(&g, base + off_glob, sizeof(g), hipMemcpyDeviceToHost, h->stream));
   for (int i = 0; i < nsys; ++i)
     HIPCHK(h, hipMemcpyAsync(&hdr[i], base + L[i].off_state, sizeof(DevState),
@@ -235,13 +297,14 @@ int ssp_autotune_batch(ssp_handle *h, int nsys, const ssp_matrix *const *A,
       if (line.rfind(key.str() + " ", 0) == 0) {
         std::istringstream f(line.substr(key.str().size()));
         std::string tag;
-        ssp_tune t{0, 0, 0, 0};
+        ssp_tune t{0, 0, 0, 0, 0};
         while (f >> tag) {
           if (tag.rfind("tile_rows=", 0) == 0) t.tile_rows = std::stoi(tag.substr(10));
           else if (tag.rfind("grid=", 0) == 0) t.grid = std::stoi(tag.substr(5));
           else if (tag.rfind("order=", 0) == 0) t.order = std::stoi(tag.substr(6));
+          else if (tag.rfind("schedule=", 0) == 0) t.schedule = std::stoi(tag.substr(9));
         }
-        if (t.grid > 0) {
+        if (t.grid > 0 || t.schedule == 1) {
           *out = t;
           return SSP_OK;
         }
@@ -267,35 +330,37 @@ int ssp_autotune_batch(ssp_handle *h, int nsys, const ssp_matrix *const *A,
   const int tiles[] = {0, 16384, 65536, 262144};
   const int grids[] = {256, 512, 1024, 2048};
   double best = 1e300;
-  ssp_tune bt{0, 512, 0, 0};
+  ssp_tune bt{0, 512, 0, 0, 0};
   int rc = SSP_OK;
-  for (int ti : tiles)
+  auto trial = [&](const ssp_tune &t) {
+    double ms = 0.0;
+    for (int rep = 0; rep < 2 && rc >= 0; ++rep) {
+      for (int i = 0; i < nsys; ++i)
+        (void)hipMemsetAsync(xs[i], 0, sizeof(double) * A[i]->n, h->stream);
+      (void)hipStreamSynchronize(h->stream);
+      auto t0 = std::chrono::steady_clock::now();
+      rc = ssp_solve_batch(h, nsys, A, b, xs.data(), s, 0.0, 4 * s, &o, &t, nullptr, nullptr,
+                           nullptr);
+      auto t1 = std::chrono::steady_clock::now();
+      if (rep == 1) ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    }
+    if (rc >= 0 && ms < best) {
+      best = ms;
+      bt = t;
+    }
+  };
+  for (int ti : tiles) {
     for (int gi : grids)
-      for (int oi = 0; oi < 2 && rc >= 0; ++oi) {
-        ssp_tune t{ti, gi, oi, 0};
-        double ms = 0.0;
-        for (int rep = 0; rep < 2 && rc >= 0; ++rep) {
-          for (int i = 0; i < nsys; ++i)
-            (void)hipMemsetAsync(xs[i], 0, sizeof(double) * A[i]->n, h->stream);
-          (void)hipStreamSynchronize(h->stream);
-          auto t0 = std::chrono::steady_clock::now();
-          rc = ssp_solve_batch(h, nsys, A, b, xs.data(), s, 0.0, 4 * s, &o, &t, nullptr, nullptr,
-                               nullptr);
-          auto t1 = std::chrono::steady_clock::now();
-          if (rep == 1) ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
-        }
-        if (rc >= 0 && ms < best) {
-          best = ms;
-          bt = t;
-        }
-      }
+      for (int oi = 0; oi < 2 && rc >= 0; ++oi) trial(ssp_tune{ti, gi, oi, 0, 0});
+    if (rc >= 0) trial(ssp_tune{ti, 0, 0, 0, 1});
+  }
   for (double *p : xs) (void)hipFree(p);
   if (rc < 0) return rc;
   *out = bt;
   if (cache_path) {
     std::ofstream f(cache_path, std::ios::app);
     f << key.str() << " tile_rows=" << bt.tile_rows << " grid=" << bt.grid
-      << " order=" << bt.order << " ms=" << best << "\n";
+      << " order=" << bt.order << " schedule=" << bt.schedule << " ms=" << best << "\n";
   }
   return SSP_OK;
 }

@@ -286,4 +286,40 @@ __global__ __launch_bounds__(kWG) void k_batch(const BatchSys *__restrict__ sys,
   }
 }
 
+// Stepped schedule: the same per-system phases, one launch pair per step.
+// k_batch_tiles runs every tile of every unfinished system's current phase
+// (work item g is tile tile_idx[g] of system tile_sys[g]); k_batch_step then
+// finishes each system's phase (one workgroup per system).  Kernel
+// boundaries order the phases, so no fences or claims are needed, and a
+// tile's arithmetic is the persistent kernel's exactly.
+template <int S>
+__global__ __launch_bounds__(kWG) void k_batch_tiles(const BatchSys *__restrict__ sys,
+                                                     const BatchSched *__restrict__ sched,
+                                                     const int *__restrict__ tile_sys,
+                                                     const int *__restrict__ tile_idx) {
+  const int i = tile_sys[blockIdx.x];
+  BatchSched sc;
+  sc.phase = sched[i].phase;
+  sc.j = sched[i].j;
+  if (sc.phase == PH_DONE) return;
+  batch_tile<S>(sys[i], sc, tile_idx[blockIdx.x]);
+}
+
+template <int S>
+__global__ __launch_bounds__(kWG) void k_batch_step(const BatchSys *__restrict__ sys,
+                                                    BatchSched *sched, BatchGlobal *glob) {
+  const int i = blockIdx.x;
+  BatchSched sc;
+  sc.phase = sched[i].phase;
+  sc.j = sched[i].j;
+  if (sc.phase == PH_DONE) return;
+  int jn = 1;
+  const int next = batch_transition<S>(sys[i], sc, &jn);
+  if (threadIdx.x == 0) {
+    sched[i].phase = next;
+    sched[i].j = jn;
+    if (next == PH_DONE) atomicAdd(&glob->ndone, 1u);
+  }
+}
+
 }  // namespace ssp
