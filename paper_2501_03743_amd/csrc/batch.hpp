@@ -159,7 +159,7 @@ __device__ int batch_transition(const BatchSys &y, const BatchSched &sc, int *jn
     } else {
       double tot[2 * S];
       reduce_partials<2 * S>(y.partials, y.ntiles, tot);
-      small_solve(st, S, tot);
+      small_solve_t<S>(st, tot);
       __syncthreads();
       if (threadIdx.x == 0) {
         j_s = 1;

@@ -117,7 +117,8 @@ __device__ void reduce_partials(const double *part, int G, double (&totals)[NP])
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int g = threadIdx.x + u * kWG;
-      v[c][u] = (g < G) ? part[(int64_t)c * G + g] : 0.0;
+      const double t = part[(int64_t)c * G + (g < G ? g : G - 1)];  // always a valid address
+      v[c][u] = (g < G) ? t : 0.0;
     }
 #pragma unroll
   for (int c = 0; c < NP; ++c) {

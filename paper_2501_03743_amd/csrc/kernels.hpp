@@ -75,7 +75,7 @@ struct EpiMpkLast {
   }
   __device__ __forceinline__ void finish(DevState *st, const double *tot) const {
     if (solve) {
-      small_solve(st, S, tot);
+      small_solve_t<S>(st, tot);
     } else if (threadIdx.x < NP) {
       st->vm[threadIdx.x] = tot[threadIdx.x];
     }

@@ -142,4 +142,144 @@ fail:
   if (tid == 0) st->status = ST_BREAKDOWN;
 }
 
+// The same s x s part for small s, in the registers of ONE thread: the same
+// operations in the same order as small_solve, without the workgroup's
+// barriers (for s <= 6 the serial arithmetic is a few hundred flops, far
+// cheaper than a dozen barriers).  Called by one thread only.
+template <int S>
+__device__ void small_solve_serial(DevState *st, const double *vm_in) {
+#pragma clang fp contract(off)
+  const double eps = 2.220446049250313e-16;  // 2^-52
+  double vm[2 * S], beta[S][S], W[S][S], L[S][S], alpha[S];
+#pragma unroll
+  for (int i = 0; i < 2 * S; ++i) vm[i] = vm_in[i];
+  const int k = st->k;
+  if (k > 0) {
+    double ap[S], Lp[S][S], rhs[2 * S];
+#pragma unroll
+    for (int i = 0; i < S; ++i) ap[i] = st->alpha[i];
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+      for (int j = 0; j < S; ++j) Lp[i][j] = st->L[i * S + j];
+    const double as = ap[S - 1];
+    if (!(fabs(as) > 1e-300) || !isfinite(as)) goto fail;
+#pragma unroll
+    for (int m = 0; m < 2 * S; ++m) rhs[m] = 0.0;
+    // rhs(s-1+i) = -(vm(i) + sum_{j<i} rhs(s-1+j) alpha(s-i+j)) / alpha(s)
+#pragma unroll
+    for (int i = 1; i <= S; ++i) {
+      double t = vm[i - 1];
+#pragma unroll
+      for (int j = 1; j <= i - 1; ++j) t += rhs[S - 2 + j] * ap[S - i + j - 1];
+      const double v = -t / as;
+      rhs[S - 2 + i] = v;
+      if (!isfinite(v)) goto fail;
+    }
+    // W_{i-1} beta = b1, b1(i,j) = -rhs(i+j-1), column by column
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+      double col[S];
+#pragma unroll
+      for (int i = 0; i < S; ++i) {
+        double v = -rhs[i + j];
+#pragma unroll
+        for (int q = 0; q < i; ++q) v -= Lp[i][q] * col[q];
+        col[i] = v / Lp[i][i];
+      }
+#pragma unroll
+      for (int i = S - 1; i >= 0; --i) {
+        double v = col[i];
+#pragma unroll
+        for (int q = i + 1; q < S; ++q) v -= Lp[q][i] * col[q];
+        col[i] = v / Lp[i][i];
+      }
+#pragma unroll
+      for (int i = 0; i < S; ++i) beta[i][j] = col[i];
+    }
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+      for (int j = 0; j < S; ++j) {
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < S; ++q) acc += (-rhs[i + q]) * beta[q][j];
+        W[i][j] = vm[i + j + 1] - acc;
+      }
+  } else {
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+      for (int j = 0; j < S; ++j) {
+        W[i][j] = vm[i + j + 1];
+        beta[i][j] = 0.0;
+      }
+  }
+  // Cholesky of the lower triangle, one column at a time
+#pragma unroll
+  for (int i = 0; i < S; ++i)
+#pragma unroll
+    for (int j = 0; j < S; ++j) L[i][j] = 0.0;
+#pragma unroll
+  for (int j = 0; j < S; ++j) {
+    const double wjj = W[j][j];
+    double d = wjj;
+#pragma unroll
+    for (int q = 0; q < j; ++q) d -= L[j][q] * L[j][q];
+    if (!isfinite(d) || d <= (double)S * eps * fabs(wjj)) goto fail;
+    L[j][j] = sqrt(d);
+#pragma unroll
+    for (int i = j + 1; i < S; ++i) {
+      double v = W[i][j];
+#pragma unroll
+      for (int q = 0; q < j; ++q) v -= L[i][q] * L[j][q];
+      v = v / L[j][j];
+      L[i][j] = v;
+      if (!isfinite(v)) goto fail;
+    }
+  }
+  // W alpha = vm(1:s)
+#pragma unroll
+  for (int i = 0; i < S; ++i) {
+    double v = vm[i];
+#pragma unroll
+    for (int q = 0; q < i; ++q) v -= L[i][q] * alpha[q];
+    alpha[i] = v / L[i][i];
+  }
+#pragma unroll
+  for (int i = S - 1; i >= 0; --i) {
+    double v = alpha[i];
+#pragma unroll
+    for (int q = i + 1; q < S; ++q) v -= L[q][i] * alpha[q];
+    alpha[i] = v / L[i][i];
+    if (!isfinite(alpha[i])) goto fail;
+  }
+#pragma unroll
+  for (int i = 0; i < 2 * S; ++i) st->vm[i] = vm[i];
+#pragma unroll
+  for (int i = 0; i < S; ++i) st->alpha[i] = alpha[i];
+#pragma unroll
+  for (int i = 0; i < S; ++i)
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+      st->beta[i * S + j] = beta[i][j];
+      st->W[i * S + j] = W[i][j];
+      st->L[i * S + j] = L[i][j];
+    }
+  return;
+fail:
+  st->status = ST_BREAKDOWN;
+}
+
+// Dispatch: serial registers for small s, the workgroup version otherwise.
+// Called by all threads of the workgroup.
+template <int S>
+__device__ __forceinline__ void small_solve_t(DevState *st, const double *vm) {
+  if constexpr (S <= 6) {
+    if (threadIdx.x == 0) small_solve_serial<S>(st, vm);
+  } else {
+    small_solve(st, S, vm);
+  }
+}
+
 }  // namespace ssp
