@@ -38,17 +38,18 @@ MAXIT = 20000
 
 def algorithmic_bytes(n, nnz):
     """Bytes one launch of each kernel class must move (FP64 values and
-    vectors, int32 indices; the 7-point matrix has a constant diagonal, so
-    the Jacobi scaling is one constant and reads no vector):
-      matrix power j < s: val + colind (12 nnz) + rowptr (4 n) + x, AZ_j, Z_{j+1} (24 n)
-      last power + moments: 12 nnz + 4 n + x, AZ_s, r (24 n) + Z(:,1..s-1) (8 (s-1) n)
-      block update: reads Z, AZ, P_old, AP_old, x, r (8 (4s + 2) n),
-                    writes P, AP, x, r, z1 (8 (2s + 3) n)
+    vectors, int32 indices).  The 7-point matrix has a constant diagonal, so
+    the Jacobi scaling is one constant c: no Z column of the block is stored,
+    each reader forms c * r or c * AZ(:,j-1) itself.
+      matrix power j < s: val + colind (12 nnz) + rowptr (4 n) + gathered input, AZ_j (16 n)
+      last power + moments: 12 nnz + 4 n + input, AZ_s, r (24 n) + AZ_1..AZ_{s-2} (8 (s-2) n)
+      block update: reads AZ, P_old, AP_old, x, r (8 (3s + 2) n),
+                    writes P, AP, x, r (8 (2s + 2) n)
     """
     return {
-        "mpk": 12 * nnz + 4 * n + 24 * n,
-        "mpk_last": 12 * nnz + 4 * n + 24 * n + 8 * (S - 1) * n,
-        "update": 8 * (4 * S + 2) * n + 8 * (2 * S + 3) * n,
+        "mpk": 12 * nnz + 4 * n + 16 * n,
+        "mpk_last": 12 * nnz + 4 * n + 24 * n + 8 * (S - 2) * n,
+        "update": 8 * (3 * S + 2) * n + 8 * (2 * S + 2) * n,
     }
 
 
@@ -420,6 +421,13 @@ def main():
                    "sstep_mixed_ir_inner1e-6": run2(s=S, precision="mixed_ir", inner_rtol=1e-6),
                    "sstep_mixed_ir_inner1e-4": run2(s=S, precision="mixed_ir", inner_rtol=1e-4),
                    "pcg_fp64": run2(method="pcg")}
+        A2.close()
+        # the same operator matrix-free (nothing stored but the two coefficients)
+        A2 = H.matrix_stencil("3d27", (N2, N2, N2))
+        run2(s=S, precision="mixed_ir")
+        config2["stencil_sstep_fp64"] = run2(s=S)
+        config2["stencil_sstep_mixed_ir"] = run2(s=S, precision="mixed_ir")
+        config2["stencil_pcg_fp64"] = run2(method="pcg")
         A2.close()
         del b2, x2, xref
 

@@ -128,7 +128,7 @@ __device__ void batch_tile(const BatchSys &y, const BatchSched &sc, int t) {
   } else if (sc.phase == PH_UPDATE) {
     UpdateCoef<S, float> c;
     c.load(y.st);
-    double v[1] = {update_rows<S, float>(c, lo, hi, y.ld, Pc, Po, y.d32, y.r32, y.pc32)};
+    double v[1] = {update_rows<S, float>(c, lo, hi, y.ld, Pc, Po, y.d32, y.r32, y.pc32, 0.0f)};
     block_store_sums<1>(v, y.partials + t, y.ntiles);
   } else if (sc.phase == PH_IRADD) {
     for (int64_t i = lo + threadIdx.x; i < hi; i += kWG) y.x[i] = y.x[i] + (double)y.d32[i];

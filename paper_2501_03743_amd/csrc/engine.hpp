@@ -177,33 +177,34 @@ inline void prof_collect(ssp_handle *h, int iters_done) {
 // Operator launch (CSR or stencil kind) with epilogue Epi, followed by the
 // finalisation kernel when Epi reduces.
 template <typename T, class Epi>
-int launch_op(ssp_handle *h, const ssp_matrix *A, const T *x, const Epi &epi, int cls) {
+int launch_op(ssp_handle *h, const ssp_matrix *A, const T *x, const Epi &epi, int cls,
+              T xs = T(1)) {
   const int G = grid_of(A);
   T *tag = nullptr;
   prof_begin(h, cls);
   switch (A->kind) {
     case 0:
       if (A->csr.variant == CSR_ROW)
-        k_csr<CSR_ROW, T, Epi><<<G, kWG, 0, h->stream>>>(csr_of(A, tag), x, epi, h->st,
+        k_csr<CSR_ROW, T, Epi><<<G, kWG, 0, h->stream>>>(csr_of(A, tag), x, xs, epi, h->st,
                                                           h->ws.partials);
       else
-        k_csr<CSR_STAGED, T, Epi><<<G, kWG, 0, h->stream>>>(csr_of(A, tag), x, epi, h->st,
+        k_csr<CSR_STAGED, T, Epi><<<G, kWG, 0, h->stream>>>(csr_of(A, tag), x, xs, epi, h->st,
                                                              h->ws.partials);
       break;
     case SSP_STENCIL_2D5:
-      k_stencil<K_2D5, T, Epi><<<G, kWG, 0, h->stream>>>(sten_of(A, tag), x, epi, h->st,
+      k_stencil<K_2D5, T, Epi><<<G, kWG, 0, h->stream>>>(sten_of(A, tag), x, xs, epi, h->st,
                                                           h->ws.partials);
       break;
     case SSP_STENCIL_3D7:
-      k_stencil<K_3D7, T, Epi><<<G, kWG, 0, h->stream>>>(sten_of(A, tag), x, epi, h->st,
+      k_stencil<K_3D7, T, Epi><<<G, kWG, 0, h->stream>>>(sten_of(A, tag), x, xs, epi, h->st,
                                                           h->ws.partials);
       break;
     case SSP_STENCIL_3D27:
-      k_stencil<K_3D27, T, Epi><<<G, kWG, 0, h->stream>>>(sten_of(A, tag), x, epi, h->st,
+      k_stencil<K_3D27, T, Epi><<<G, kWG, 0, h->stream>>>(sten_of(A, tag), x, xs, epi, h->st,
                                                            h->ws.partials);
       break;
     case SSP_STENCIL_3D7_VARK:
-      k_stencil<K_VARK, T, Epi><<<G, kWG, 0, h->stream>>>(sten_of(A, tag), x, epi, h->st,
+      k_stencil<K_VARK, T, Epi><<<G, kWG, 0, h->stream>>>(sten_of(A, tag), x, xs, epi, h->st,
                                                            h->ws.partials);
       break;
     default:
@@ -234,17 +235,30 @@ int sstep_iteration(ssp_handle *h, const ssp_matrix *A, const IterBufs<T> &B, in
   T *Po = (k % 2 == 0) ? B.P1 : B.P2;
   T *tag = nullptr;
   const Prec<T> pc = prec_of(A, tag);
+  // constant Jacobi scaling c (or none, c = 1): the Z columns are never
+  // stored; each reader forms c * r or c * AZ(:,j-1), the same rounded values
+  const T zc = pc.dinv ? T(0) : pc.dc;
   for (int j = 1; j <= S; ++j) {
-    const T *zin = Pc + (int64_t)(j - 1) * B.ld;
+    const T *zin;
+    T xs = T(1);
+    if (zc == T(0)) {
+      zin = Pc + (int64_t)(j - 1) * B.ld;
+    } else {
+      zin = (j == 1) ? B.r : Pc + (int64_t)(S + j - 2) * B.ld;
+      xs = zc;
+    }
     T *az = Pc + (int64_t)(S + j - 1) * B.ld;
     int rc;
-    if (j < S) rc = launch_op<T>(h, A, zin, EpiMpk<T>{az, Pc + (int64_t)j * B.ld, pc}, 0);
-    else rc = launch_op<T>(h, A, zin, EpiMpkLast<S, T>{az, Pc, B.ld, B.r, 1}, 1);
+    if (j < S)
+      rc = launch_op<T>(h, A, zin,
+                        EpiMpk<T>{az, zc == T(0) ? Pc + (int64_t)j * B.ld : nullptr, pc}, 0, xs);
+    else
+      rc = launch_op<T>(h, A, zin, EpiMpkLast<S, T>{az, Pc, B.ld, B.r, 1, zc}, 1, xs);
     if (rc) return rc;
   }
   const int G = grid_rows(A->n);
   prof_begin(h, 2);
-  k_update<S, T><<<G, kWG, 0, h->stream>>>(A->n, B.ld, Pc, Po, B.x, B.r, pc, h->st,
+  k_update<S, T><<<G, kWG, 0, h->stream>>>(A->n, B.ld, Pc, Po, B.x, B.r, pc, zc, h->st,
                                             h->ws.partials);
   k_finalize<FinUpdate><<<1, kWG, 0, h->stream>>>(FinUpdate{h->ws.hist}, h->st, h->ws.partials,
                                                   G);

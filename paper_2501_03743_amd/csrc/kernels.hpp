@@ -37,6 +37,9 @@ struct EpiStore {
 };
 
 // Matrix powers, power j < s (Alg. 4): AZ(:,j) = A Z(:,j), Z(:,j+1) = B^-1 AZ(:,j).
+// With a constant Jacobi scaling c, Z(:,j+1) = c AZ(:,j) is not stored
+// (znext = nullptr): its readers form c * AZ(i,j) themselves, the same
+// rounded value.
 template <typename T>
 struct EpiMpk {
   static constexpr int NP = 0;
@@ -45,7 +48,7 @@ struct EpiMpk {
   Prec<T> pc;
   __device__ __forceinline__ void row(int64_t i, T v, double *) const {
     az[i] = v;
-    znext[i] = pc.apply(i, v);
+    if (znext) znext[i] = pc.apply(i, v);
   }
   __device__ __forceinline__ void finish(DevState *, const double *) const {}
 };
@@ -58,17 +61,23 @@ struct EpiMpkLast {
   static constexpr int NP = 2 * S;
   static constexpr bool kCheck = true;
   T *az;
-  const T *Z;       // column a at Z + a*ld
+  const T *Z;       // the block: Z(:,a) at column a-1, AZ(:,a) at column S+a-1
   int64_t ld;
   const T *r;
   int solve;        // 0: only store vm (the stand-alone Alg. 4 + Alg. 5 call)
+  T zc;             // 0: Z stored; else the constant Jacobi scaling c, with
+                    // Z(:,1) = c r and Z(:,a) = c AZ(:,a-1) formed here
   __device__ __forceinline__ void row(int64_t i, T v, double *part) const {
+#pragma clang fp contract(off)
     az[i] = v;
-    const double ri = (double)r[i];
+    const T rt = r[i];
+    const double ri = (double)rt;
     const double vi = (double)v;
 #pragma unroll
     for (int a = 0; a < S; ++a) {
-      const double za = (double)Z[(int64_t)a * ld + i];
+      const double za = (zc == T(0)) ? (double)Z[(int64_t)a * ld + i]
+                        : (a == 0) ? (double)(zc * rt)
+                                   : (double)(zc * Z[(int64_t)(S + a - 1) * ld + i]);
       part[a] += za * ri;
       part[S + a] += za * vi;
     }
@@ -99,10 +108,18 @@ struct LastPre {
 };
 template <int S, typename T>
 __device__ __forceinline__ LastPre<S> epi_pre(const EpiMpkLast<S, T> &e, int64_t i) {
+#pragma clang fp contract(off)
   LastPre<S> p;
+  const T ri = e.r[i];
+  if (e.zc == T(0)) {
 #pragma unroll
-  for (int a = 0; a < S; ++a) p.z[a] = (double)e.Z[(int64_t)a * e.ld + i];
-  p.r = (double)e.r[i];
+    for (int a = 0; a < S; ++a) p.z[a] = (double)e.Z[(int64_t)a * e.ld + i];
+  } else {
+    p.z[0] = (double)(e.zc * ri);
+#pragma unroll
+    for (int a = 1; a < S; ++a) p.z[a] = (double)(e.zc * e.Z[(int64_t)(S + a - 1) * e.ld + i]);
+  }
+  p.r = (double)ri;
   return p;
 }
 template <int S, typename T>
@@ -332,7 +349,7 @@ __global__ __launch_bounds__(kWG) void k_finalize(Fin fin, DevState *st, const d
 }
 
 template <int VARIANT, typename T, class Epi>
-__global__ __launch_bounds__(kWG) void k_csr(CsrArgs<T> A, const T *__restrict__ x, Epi epi,
+__global__ __launch_bounds__(kWG) void k_csr(CsrArgs<T> A, const T *__restrict__ x, T xs, Epi epi,
                                              DevState *st, double *partials) {
   if (Epi::kCheck && st->status != ST_RUNNING) return;
   double part[Epi::NP > 0 ? Epi::NP : 1];
@@ -340,12 +357,12 @@ __global__ __launch_bounds__(kWG) void k_csr(CsrArgs<T> A, const T *__restrict__
   for (int c = 0; c < (Epi::NP > 0 ? Epi::NP : 1); ++c) part[c] = 0.0;
   csr_rows<VARIANT>(
       A, x, [&](int64_t i) { return epi_pre(epi, i); },
-      [&](int64_t i, T v, const auto &p) { epi_row(epi, i, v, p, part); });
+      [&](int64_t i, T v, const auto &p) { epi_row(epi, i, v, p, part); }, xs);
   epi_tail<Epi>(part, partials);
 }
 
 template <int KIND, typename T, class Epi>
-__global__ __launch_bounds__(kWG) void k_stencil(StencilArgs<T> S, const T *__restrict__ x,
+__global__ __launch_bounds__(kWG) void k_stencil(StencilArgs<T> S, const T *__restrict__ x, T xs,
                                                  Epi epi, DevState *st, double *partials) {
   if (Epi::kCheck && st->status != ST_RUNNING) return;
   double part[Epi::NP > 0 ? Epi::NP : 1];
@@ -353,7 +370,7 @@ __global__ __launch_bounds__(kWG) void k_stencil(StencilArgs<T> S, const T *__re
   for (int c = 0; c < (Epi::NP > 0 ? Epi::NP : 1); ++c) part[c] = 0.0;
   int64_t p0, p1;
   block_chunk(S.n, logical_block(), gridDim.x, p0, p1);
-  stencil_rows<KIND>(S, x, p0, p1, [&](int64_t i, T v) { epi.row(i, v, part); });
+  stencil_rows<KIND>(S, x, p0, p1, [&](int64_t i, T v) { epi.row(i, v, part); }, xs);
   epi_tail<Epi>(part, partials);
 }
 
@@ -385,19 +402,33 @@ struct UpdateCoef {
 };
 
 // The rows [lo, hi) of the block update; returns this thread's partial ||r||^2.
+// zc = 0: Z is stored in the block and z1 = B^-1 r_new is written for the
+// next matrix powers; zc = c (constant Jacobi scaling): Z(:,1) = c r and
+// Z(:,j) = c AZ(:,j-1) are formed from values the update reads anyway, and
+// no z1 is written.
 template <int S, typename T>
 __device__ __forceinline__ double update_rows(const UpdateCoef<S, T> &c, int64_t lo, int64_t hi,
                                               int64_t ld, T *__restrict__ Pc,
                                               T *__restrict__ Po, T *__restrict__ x,
-                                              T *__restrict__ r, const Prec<T> &pc) {
+                                              T *__restrict__ r, const Prec<T> &pc, T zc) {
 #pragma clang fp contract(off)
   double part = 0.0;
   for (int64_t i = lo + threadIdx.x; i < hi; i += kWG) {
     double p[S], ap[S];
+    const T r0 = r[i];
+    T azs[S];
 #pragma unroll
     for (int j = 0; j < S; ++j) {
-      p[j] = (double)Pc[(int64_t)j * ld + i];
-      ap[j] = (double)Pc[(int64_t)(S + j) * ld + i];
+      azs[j] = Pc[(int64_t)(S + j) * ld + i];
+      ap[j] = (double)azs[j];
+    }
+    if (zc == T(0)) {
+#pragma unroll
+      for (int j = 0; j < S; ++j) p[j] = (double)Pc[(int64_t)j * ld + i];
+    } else {
+      p[0] = (double)(zc * r0);
+#pragma unroll
+      for (int j = 1; j < S; ++j) p[j] = (double)(zc * azs[j - 1]);
     }
     if (c.k > 0) {
       double po[S], apo[S];
@@ -422,6 +453,10 @@ __device__ __forceinline__ double update_rows(const UpdateCoef<S, T> &c, int64_t
         p[j] = (double)as;
         ap[j] = (double)bs;
       }
+    } else if (zc != T(0)) {
+      // k = 0: P = Z must be stored for the next iteration's P_old beta
+#pragma unroll
+      for (int j = 0; j < S; ++j) Pc[(int64_t)j * ld + i] = (T)p[j];
     }
     double dx = 0.0, dr = 0.0;
 #pragma unroll
@@ -432,10 +467,10 @@ __device__ __forceinline__ double update_rows(const UpdateCoef<S, T> &c, int64_t
       dr += u;
     }
     const T xi = (T)((double)x[i] + dx);
-    const T ri = (T)((double)r[i] - dr);
+    const T ri = (T)((double)r0 - dr);
     x[i] = xi;
     r[i] = ri;
-    Po[i] = pc.apply(i, ri);
+    if (zc == T(0)) Po[i] = pc.apply(i, ri);
     part += (double)ri * (double)ri;
   }
   return part;
@@ -444,14 +479,14 @@ __device__ __forceinline__ double update_rows(const UpdateCoef<S, T> &c, int64_t
 template <int S, typename T>
 __global__ __launch_bounds__(kWG) void k_update(int64_t n, int64_t ld, T *__restrict__ Pc,
                                                 T *__restrict__ Po, T *__restrict__ x,
-                                                T *__restrict__ r, Prec<T> pc, DevState *st,
+                                                T *__restrict__ r, Prec<T> pc, T zc, DevState *st,
                                                 double *partials) {
   if (st->status != ST_RUNNING) return;
   UpdateCoef<S, T> c;
   c.load(st);
   int64_t lo, hi;
   block_chunk(n, logical_block(), gridDim.x, lo, hi);
-  double v[1] = {update_rows<S, T>(c, lo, hi, ld, Pc, Po, x, r, pc)};
+  double v[1] = {update_rows<S, T>(c, lo, hi, ld, Pc, Po, x, r, pc, zc)};
   block_store_sums<1>(v, partials + logical_block(), gridDim.x);
 }
 

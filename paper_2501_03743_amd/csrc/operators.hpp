@@ -54,7 +54,7 @@ struct Prec {
 // per-thread loop.  Walks row blocks [rb0, rb1); all threads must call it.
 template <typename T, class F>
 __device__ __forceinline__ void csr_rows_staged(const CsrArgs<T> &A, const T *__restrict__ x,
-                                                int64_t rb0, int64_t rb1, F &&f) {
+                                                int64_t rb0, int64_t rb1, F &&f, T xs = T(1)) {
 #pragma clang fp contract(off)
   constexpr int kPer = kCsrLds / kWG;
   __shared__ T prod[kCsrLds];
@@ -78,7 +78,7 @@ __device__ __forceinline__ void csr_rows_staged(const CsrArgs<T> &A, const T *__
         vv[u] = A.val[e0 + ec];
       }
 #pragma unroll
-      for (int u = 0; u < kPer; ++u) vv[u] = vv[u] * x[ci[u]];
+      for (int u = 0; u < kPer; ++u) vv[u] = vv[u] * (xs * x[ci[u]]);
 #pragma unroll
       for (int u = 0; u < kPer; ++u) {
         const int e = threadIdx.x + u * kWG;
@@ -96,7 +96,7 @@ __device__ __forceinline__ void csr_rows_staged(const CsrArgs<T> &A, const T *__
       for (int64_t row = r0 + threadIdx.x; row < r1; row += kWG) {
         T acc = 0;
         for (int e = A.rowptr[row]; e < A.rowptr[row + 1]; ++e) {
-          const T t = A.val[e] * x[A.colind[e]];
+          const T t = A.val[e] * (xs * x[A.colind[e]]);
           acc += t;
         }
         f(row, acc);
@@ -112,7 +112,7 @@ __device__ __forceinline__ void csr_rows_staged(const CsrArgs<T> &A, const T *__
 // therefore has the same terms, order and rounding as a sequential product.
 template <typename T, int U>
 __device__ __forceinline__ T csr_row_sum(const CsrArgs<T> &A, const T *__restrict__ x, int a,
-                                         int b) {
+                                         int b, T xs) {
 #pragma clang fp contract(off)
   T acc = 0;
   for (int e = a; e < b; e += U) {
@@ -125,7 +125,7 @@ __device__ __forceinline__ T csr_row_sum(const CsrArgs<T> &A, const T *__restric
       vv[u] = A.val[eu];
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u) vv[u] = vv[u] * x[ci[u]];
+    for (int u = 0; u < U; ++u) vv[u] = vv[u] * (xs * x[ci[u]]);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const T t = acc + vv[u];
@@ -144,12 +144,13 @@ struct NoPre {};
 // as a sequential product.
 template <typename T, class Pre, class F>
 __device__ __forceinline__ void csr_rows_direct(const CsrArgs<T> &A, const T *__restrict__ x,
-                                                int64_t r0, int64_t r1, Pre &&pre, F &&f) {
+                                                int64_t r0, int64_t r1, Pre &&pre, F &&f,
+                                                T xs = T(1)) {
   constexpr int U = 8;
   for (int64_t row = r0 + threadIdx.x; row < r1; row += kWG) {
     const int a = A.rowptr[row], b = A.rowptr[row + 1];
     const auto p = pre(row);
-    f(row, csr_row_sum<T, U>(A, x, a, b), p);
+    f(row, csr_row_sum<T, U>(A, x, a, b, xs), p);
   }
 }
 
@@ -167,15 +168,15 @@ __device__ __forceinline__ void csr_rows_direct(const CsrArgs<T> &A, const T *__
 // staging buffer nor its registers (occupancy).
 template <int VARIANT, typename T, class Pre, class F>
 __device__ __forceinline__ void csr_rows(const CsrArgs<T> &A, const T *__restrict__ x, Pre &&pre,
-                                         F &&f) {
+                                         F &&f, T xs) {
   if constexpr (VARIANT == CSR_ROW) {
     int64_t r0, r1;
     block_chunk(A.n, logical_block(), gridDim.x, r0, r1);
-    csr_rows_direct(A, x, r0, r1, pre, f);
+    csr_rows_direct(A, x, r0, r1, pre, f, xs);
   } else {
     int64_t rb0, rb1;
     block_chunk(A.nrb, logical_block(), gridDim.x, rb0, rb1);
-    csr_rows_staged(A, x, rb0, rb1, [&](int64_t i, T v) { f(i, v, pre(i)); });
+    csr_rows_staged(A, x, rb0, rb1, [&](int64_t i, T v) { f(i, v, pre(i)); }, xs);
   }
 }
 
@@ -190,9 +191,13 @@ __device__ __forceinline__ T face_weight(T kp, T kq) {
 
 // Matrix-free grid operators over points [p0, p1); neighbour order follows
 // the definitions (Dirichlet: neighbours outside the grid are absent).
+// Every visitor applies the operator to xs * x, forming each xs * x[q] as a
+// rounded value first: with xs = 1 that is x itself, and with the constant
+// Jacobi scaling c it reproduces the product of the stored vector z = c * x
+// bit for bit, so a block column z never has to be written.
 template <int KIND, typename T, class F>
 __device__ __forceinline__ void stencil_rows(const StencilArgs<T> &S, const T *__restrict__ x,
-                                             int64_t p0, int64_t p1, F &&f) {
+                                             int64_t p0, int64_t p1, F &&f, T xs = T(1)) {
 #pragma clang fp contract(off)
   const int nx = S.nx, ny = S.ny, nz = S.nz;
   const int64_t sy = nx, sz = (int64_t)nx * ny;
@@ -213,7 +218,7 @@ __device__ __forceinline__ void stencil_rows(const StencilArgs<T> &S, const T *_
         const bool ok = z + dz >= 0 && z + dz < nz && yq + dy >= 0 && yq + dy < ny &&
                         xq + dx >= 0 && xq + dx < nx && t != 13;
         in[t] = ok;
-        v[t] = x[ok ? p + dz * sz + dy * sy + dx : p];
+        v[t] = xs * x[ok ? p + dz * sz + dy * sy + dx : p];
       }
       T nb = 0;
 #pragma unroll
@@ -233,9 +238,9 @@ __device__ __forceinline__ void stencil_rows(const StencilArgs<T> &S, const T *_
       for (int f6 = 0; f6 < 6; ++f6) {
         const int64_t qq = in[f6] ? q[f6] : p;
         kq[f6] = S.k[qq];
-        xv[f6] = x[qq];
+        xv[f6] = xs * x[qq];
       }
-      const T xp = x[p];
+      const T xp = xs * x[p];
       T dsum = 0, nb = 0;
 #pragma unroll
       for (int f6 = 0; f6 < 6; ++f6) {
@@ -249,14 +254,14 @@ __device__ __forceinline__ void stencil_rows(const StencilArgs<T> &S, const T *_
       const T d = dsum * xp;
       acc = d - nb;
     } else {
-      const T xm = x[xq > 0 ? p - 1 : p], xpl = x[xq < nx - 1 ? p + 1 : p];
-      const T ym = x[yq > 0 ? p - sy : p], ypl = x[yq < ny - 1 ? p + sy : p];
+      const T xm = xs * x[xq > 0 ? p - 1 : p], xpl = xs * x[xq < nx - 1 ? p + 1 : p];
+      const T ym = xs * x[yq > 0 ? p - sy : p], ypl = xs * x[yq < ny - 1 ? p + sy : p];
       T zm = 0, zpl = 0;
       if constexpr (KIND == K_3D7) {
-        zm = x[z > 0 ? p - sz : p];
-        zpl = x[z < nz - 1 ? p + sz : p];
+        zm = xs * x[z > 0 ? p - sz : p];
+        zpl = xs * x[z < nz - 1 ? p + sz : p];
       }
-      const T xc = x[p];
+      const T xc = xs * x[p];
       T nb = 0;
       nb = xq > 0 ? nb + xm : nb;
       nb = xq < nx - 1 ? nb + xpl : nb;
