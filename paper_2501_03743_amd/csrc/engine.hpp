@@ -125,7 +125,15 @@ inline int grid_rows(int64_t n) {
   return (int)g;
 }
 
+inline bool tiled_of(const ssp_matrix *A, Tiling3 &t) {
+  return A->kind != 0 && stencil_tiling(A->kind == SSP_STENCIL_3D7 ? K_3D7
+                                        : A->kind == SSP_STENCIL_3D27 ? K_3D27 : 0,
+                                        A->sten.nx, A->sten.ny, A->sten.nz, t);
+}
+
 inline int grid_of(const ssp_matrix *A) {
+  Tiling3 t;
+  if (tiled_of(A, t)) return t.ntx * t.nty * t.ntz;
   if (A->kind == 0 && A->csr.variant == CSR_STAGED) {
     int64_t g = A->csr.nrb;
     if (g > kGridMax) g = kGridMax;
@@ -196,13 +204,26 @@ int launch_op(ssp_handle *h, const ssp_matrix *A, const T *x, const Epi &epi, in
                                                           h->ws.partials);
       break;
     case SSP_STENCIL_3D7:
-      k_stencil<K_3D7, T, Epi><<<G, kWG, 0, h->stream>>>(sten_of(A, tag), x, xs, epi, h->st,
-                                                          h->ws.partials);
+    case SSP_STENCIL_3D27: {
+      Tiling3 tl;
+      const bool tiled = tiled_of(A, tl);
+      if (A->kind == SSP_STENCIL_3D7) {
+        if (tiled)
+          k_stencil_tiled<K_3D7, T, Epi><<<G, kWG, 0, h->stream>>>(sten_of(A, tag), x, xs, epi,
+                                                                    h->st, h->ws.partials, tl);
+        else
+          k_stencil<K_3D7, T, Epi><<<G, kWG, 0, h->stream>>>(sten_of(A, tag), x, xs, epi, h->st,
+                                                              h->ws.partials);
+      } else {
+        if (tiled)
+          k_stencil_tiled<K_3D27, T, Epi><<<G, kWG, 0, h->stream>>>(sten_of(A, tag), x, xs, epi,
+                                                                     h->st, h->ws.partials, tl);
+        else
+          k_stencil<K_3D27, T, Epi><<<G, kWG, 0, h->stream>>>(sten_of(A, tag), x, xs, epi,
+                                                               h->st, h->ws.partials);
+      }
       break;
-    case SSP_STENCIL_3D27:
-      k_stencil<K_3D27, T, Epi><<<G, kWG, 0, h->stream>>>(sten_of(A, tag), x, xs, epi, h->st,
-                                                           h->ws.partials);
-      break;
+    }
     case SSP_STENCIL_3D7_VARK:
       k_stencil<K_VARK, T, Epi><<<G, kWG, 0, h->stream>>>(sten_of(A, tag), x, xs, epi, h->st,
                                                            h->ws.partials);

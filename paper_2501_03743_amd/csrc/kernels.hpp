@@ -374,6 +374,87 @@ __global__ __launch_bounds__(kWG) void k_stencil(StencilArgs<T> S, const T *__re
   epi_tail<Epi>(part, partials);
 }
 
+// LDS-staged 3D stencils (7- and 27-point, constant coefficients): the same
+// operator and epilogues as k_stencil, the same terms in the same order per
+// point (neighbours outside the grid masked out), but each x value is
+// brought into LDS once per plane tile instead of being gathered through the
+// caches by every neighbour.
+template <int KIND, typename T, class Epi>
+__global__ __launch_bounds__(kWG) void k_stencil_tiled(StencilArgs<T> S, const T *__restrict__ x,
+                                                       T xs, Epi epi, DevState *st,
+                                                       double *partials, Tiling3 tl) {
+#pragma clang fp contract(off)
+  if (Epi::kCheck && st->status != ST_RUNNING) return;
+  constexpr int HX = kTX + 2, HY = kTY + 2;
+  __shared__ T pl[3][HY][HX];
+  double part[Epi::NP > 0 ? Epi::NP : 1];
+#pragma unroll
+  for (int c = 0; c < (Epi::NP > 0 ? Epi::NP : 1); ++c) part[c] = 0.0;
+  const int nx = S.nx, ny = S.ny, nz = S.nz;
+  const int b = logical_block();
+  const int tx = b % tl.ntx, ty = (b / tl.ntx) % tl.nty, tz = b / (tl.ntx * tl.nty);
+  const int x0 = tx * kTX, y0 = ty * kTY, z0 = tz * tl.zchunk;
+  const int z1 = (z0 + tl.zchunk < nz) ? z0 + tl.zchunk : nz;
+  const int lx = threadIdx.x % kTX, ly = threadIdx.x / kTX;
+  const int gx = x0 + lx, gy = y0 + ly;
+  const bool mine = gx < nx && gy < ny;
+  const int64_t sy = nx, sz = (int64_t)nx * ny;
+  // plane z (z >= -1) into slot (z + 3) % 3; cells outside the grid hold 0
+  // and are never summed
+  auto load = [&](int z) {
+    T(*dst)[HX] = pl[(z + 3) % 3];
+    for (int e = threadIdx.x; e < HX * HY; e += kWG) {
+      const int hy = e / HX, hx = e - hy * HX;
+      const int qx = x0 + hx - 1, qy = y0 + hy - 1;
+      const bool ok = z >= 0 && z < nz && qx >= 0 && qx < nx && qy >= 0 && qy < ny;
+      const int64_t q = ok ? (int64_t)z * sz + (int64_t)qy * sy + qx : 0;
+      const T v = xs * x[q];
+      dst[hy][hx] = ok ? v : T(0);
+    }
+  };
+  if (z0 < z1) {
+    load(z0 - 1);
+    load(z0);
+  }
+  for (int z = z0; z < z1; ++z) {
+    load(z + 1);
+    __syncthreads();
+    if (mine) {
+      const int sm = (z + 2) % 3, sc = z % 3, sp = (z + 1) % 3;
+      T acc;
+      if constexpr (KIND == K_3D27) {
+        T nb = 0;
+#pragma unroll
+        for (int t = 0; t < 27; ++t) {
+          const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+          const bool ok = t != 13 && z + dz >= 0 && z + dz < nz && gy + dy >= 0 &&
+                          gy + dy < ny && gx + dx >= 0 && gx + dx < nx;
+          const int sl = dz < 0 ? sm : (dz == 0 ? sc : sp);
+          const T u = nb + pl[sl][ly + 1 + dy][lx + 1 + dx];
+          nb = ok ? u : nb;
+        }
+        const T d = S.diag * pl[sc][ly + 1][lx + 1];
+        const T o = S.off * nb;
+        acc = d + o;
+      } else {
+        T nb = 0;
+        nb = gx > 0 ? nb + pl[sc][ly + 1][lx] : nb;
+        nb = gx < nx - 1 ? nb + pl[sc][ly + 1][lx + 2] : nb;
+        nb = gy > 0 ? nb + pl[sc][ly][lx + 1] : nb;
+        nb = gy < ny - 1 ? nb + pl[sc][ly + 2][lx + 1] : nb;
+        nb = z > 0 ? nb + pl[sm][ly + 1][lx + 1] : nb;
+        nb = z < nz - 1 ? nb + pl[sp][ly + 1][lx + 1] : nb;
+        const T d = S.diag * pl[sc][ly + 1][lx + 1];
+        const T o = S.off * nb;
+        acc = d + o;
+      }
+      epi.row((int64_t)z * sz + (int64_t)gy * sy + gx, acc, part);
+    }
+    __syncthreads();
+  }
+  epi_tail<Epi>(part, partials);
+}
+
 // Fused block update (Alg. 3, in the order of its four update lines), one
 // thread per row computing all s outputs, arithmetic in FP64:
 //   P  = Z  + P_old  beta          (skipped at k = 0: P_old = 0)
