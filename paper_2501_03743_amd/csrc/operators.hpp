@@ -147,10 +147,18 @@ __device__ __forceinline__ void csr_rows_direct(const CsrArgs<T> &A, const T *__
                                                 int64_t r0, int64_t r1, Pre &&pre, F &&f,
                                                 T xs = T(1)) {
   constexpr int U = 8;
-  for (int64_t row = r0 + threadIdx.x; row < r1; row += kWG) {
-    const int a = A.rowptr[row], b = A.rowptr[row + 1];
+  int64_t row = r0 + threadIdx.x;
+  if (row >= r1) return;
+  int a = A.rowptr[row], b = A.rowptr[row + 1];
+  for (; row < r1; row += kWG) {
+    // the next row's pointers are loaded before this row's entries, so the
+    // two load chains overlap (the last step re-reads a valid pointer)
+    const int64_t nr = (row + kWG < r1) ? row + kWG : row;
+    const int na = A.rowptr[nr], nb = A.rowptr[nr + 1];
     const auto p = pre(row);
     f(row, csr_row_sum<T, U>(A, x, a, b, xs), p);
+    a = na;
+    b = nb;
   }
 }
 
