@@ -383,6 +383,61 @@ def main():
     spmv["csr_best_gbs"] = plain_bytes / (min(spmv["csr_staged_ms"], spmv["csr_row_ms"]) * 1e-3) / 1e9
     spmv["stencil_gbs"] = 16 * n / (spmv["stencil_ms"] * 1e-3) / 1e9
 
+    # achievable bandwidth: a device-to-device copy of 1 GiB (read + write)
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * src.numel() * 8 / (e0.elapsed_time(e1) / 5 * 1e-3) / 1e9
+    del src, dst
+
+    # matrix powers at 256^3 (the 1.4 GB CSR matrix does not fit the 256 MB
+    # Infinity Cache): per-launch HBM rate over 10 profiled outer iterations
+    N3 = 256
+    A3 = H.matrix_csr_from_stencil("3d7", (N3, N3, N3))
+    b3 = torch.from_numpy(wl.normal_rhs(N3 ** 3, SEED)).cuda()
+    x3 = torch.zeros_like(b3)
+    H.solve(A3, b3, x3, s=S, fixed_outer=2)
+    x3.zero_()
+    r3 = H.solve(A3, b3, x3, s=S, fixed_outer=10, profile=True)
+    ab3 = algorithmic_bytes(N3 ** 3, A3.nnz)
+    mpk3_ms = r3.profile["ms"][0] / max(r3.profile["launches"][0], 1)
+    upd3_ms = r3.profile["ms"][2] / max(r3.profile["launches"][2], 1)
+    big = {"workload": "3D 7-point 256^3 CSR (n=16777216), s=4, 10 outer iterations",
+           "mpk_gbs": ab3["mpk"] / (mpk3_ms * 1e-3) / 1e9,
+           "mpk_frac_of_peak": ab3["mpk"] / (mpk3_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "update_gbs": ab3["update"] / (upd3_ms * 1e-3) / 1e9}
+    A3.close()
+    del b3, x3
+
+    # 2D 5-point 64^2 (everything cache-resident, launch-bound): x* ~ U(-1,1)
+    # from seeds 0..4, b = A x*, s = 4 and standard PCG
+    small = []
+    A0 = H.matrix_csr(*[torch.from_numpy(a).cuda() for a in wl.stencil_csr("2d5", (64, 64))],
+                      flags=sstep.COPY)
+    csr0 = wl.stencil_csr("2d5", (64, 64))
+    for seed in range(5):
+        b0 = torch.from_numpy(wl.csr_matvec(csr0, wl.uniform_solution(64 * 64, seed))).cuda()
+        row = {"seed": seed}
+        for name, kw in (("sstep", {"s": S}), ("pcg", {"method": "pcg"})):
+            x0 = torch.zeros_like(b0)
+            H.solve(A0, b0, x0, rtol=RTOL, **kw)
+            x0.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rr = H.solve(A0, b0, x0, rtol=RTOL, **kw)
+            torch.cuda.synchronize()
+            row[name + "_ms"] = 1e3 * (time.perf_counter() - t0)
+            row[name + "_iterations"] = rr.cg_equiv if name == "sstep" else rr.outer
+        small.append(row)
+    A0.close()
+
     per_s = {}
     for s in (1, 2, 8):
         t, r = timed(lambda: solve(s=s), reps=2)
@@ -473,6 +528,10 @@ def main():
             "pcg_stencil_tts_s": stcg_t, "pcg_stencil_iterations": stcg_r.outer,
             "sstep_csr_by_s": per_s,
             "spmv": spmv,
+            "copy_gbs": copy_gbs,
+            "mpk_frac_of_copy": achieved / copy_gbs,
+            "csr_3d7_256": big,
+            "config_2d5_64": small,
         },
         "config_27pt_256_mixed": config2,
         "config_batch32": config3,

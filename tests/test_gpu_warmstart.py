@@ -118,6 +118,21 @@ def test_learned_warm_start_gain(H):
     rec = ws.evaluate(H, model, list(range(20000, 20024)), sweeps=16)
     summ = ws.summarize(rec)
     print("warm start 32^3:", summ)
+    # spot checks against the FP64 oracle: the warm-started solution solves
+    # the same system (both to rtol 1e-8; the difference is bounded by the
+    # condition number times the tolerance)
+    import oracle
+    for seed in (20000, 20001, 20002):
+        logk, k, f, b = wl.warm_start_problem(shape, seed)
+        A = H.matrix_stencil("3d7_vark", shape, k=k)
+        x = model.predict(logk, f)
+        r = H.solve(A, b, x, s=4, rtol=1e-8, warm_start=True, warm_sweeps=16)
+        A.close()
+        ref = oracle.sstep(oracle.Operator("3d7_vark", shape, k=k.cpu().numpy()), b.cpu().numpy(),
+                           4, rtol=1e-8)
+        err = np.linalg.norm(x.cpu().numpy() - ref.x) / np.linalg.norm(ref.x)
+        print("seed %d: |x - x_oracle| / |x_oracle| = %.2e" % (seed, err))
+        assert r.status == 0 and ref.status == 0 and err < 1e-5, (seed, err)
     model.close()
     assert summ["true_rel_max_warm"] <= 1.5e-8 and summ["true_rel_max_zero"] <= 1.5e-8
     assert summ["iteration_gain"] > 0.05, summ
