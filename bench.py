@@ -367,9 +367,9 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
-    spmv = {"csr_autotuned_ms": spmv_ms(A), "stencil_ms": spmv_ms(As)}
+    spmv = {"csr_autotuned_ms": spmv_ms(A), "csr_form": A.csr_form, "stencil_ms": spmv_ms(As)}
     saved = os.environ.get("SSP_CSR_VARIANT")
-    for v, name in ((0, "csr_staged_ms"), (1, "csr_row_ms")):
+    for v, name in ((0, "csr_staged_ms"), (1, "csr_row_ms"), (2, "csr_sell_ms")):
         os.environ["SSP_CSR_VARIANT"] = str(v)
         Mv = H.matrix_csr_from_stencil("3d7", (N, N, N))
         spmv[name] = spmv_ms(Mv)
@@ -380,7 +380,8 @@ def main():
         os.environ["SSP_CSR_VARIANT"] = saved
     plain_bytes = 12 * nnz + 4 * n + 16 * n
     spmv["csr_plain_bytes"] = plain_bytes
-    spmv["csr_best_gbs"] = plain_bytes / (min(spmv["csr_staged_ms"], spmv["csr_row_ms"]) * 1e-3) / 1e9
+    spmv["csr_best_gbs"] = plain_bytes / (min(spmv["csr_staged_ms"], spmv["csr_row_ms"],
+                                              spmv["csr_sell_ms"]) * 1e-3) / 1e9
     spmv["stencil_gbs"] = 16 * n / (spmv["stencil_ms"] * 1e-3) / 1e9
 
     # achievable bandwidth: a device-to-device copy of 1 GiB (read + write)

@@ -34,7 +34,20 @@ int ensure_fp32(ssp_handle *h, ssp_matrix *A) {
     k_to_float<<<nbz, kWG, 0, h->stream>>>(A->nnz, A->csr.val, A->val32);
     LAUNCHCHK(h);
     A->csr32 = CsrArgs<float>{A->csr.n, A->csr.rowptr, A->csr.colind, A->val32,
-                              A->csr.rows_per_rb, A->csr.nrb, A->csr.variant};
+                              A->csr.rows_per_rb, A->csr.nrb, A->csr.variant,
+                              A->csr.sell_col, nullptr, A->csr.slice_off, A->csr.slice_w,
+                              A->csr.nslices};
+    if (A->sell_val) {
+      const int64_t ne = A->sell_entries;
+      if (hipMalloc(&A->sell_val32, sizeof(float) * ne) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(h, SSP_ENOMEM, "FP32 sliced-ELL allocation failed");
+      }
+      k_to_float<<<(unsigned)((ne + kWG - 1) / kWG), kWG, 0, h->stream>>>(ne, A->sell_val,
+                                                                           A->sell_val32);
+      LAUNCHCHK(h);
+      A->csr32.sell_val = A->sell_val32;
+    }
   } else {
     const StencilArgs<double> &S = A->sten;
     A->sten32 = StencilArgs<float>{S.n, S.nx, S.ny, S.nz, S.fx, S.fy, (float)S.diag,
@@ -217,14 +230,15 @@ int finish_solve(ssp_handle *h, const ssp_matrix *A, const double *b, double *x,
   return status_code(status);
 }
 
-// Both CSR kernels give bitwise-identical products; pick the faster one for
-// this matrix by timing single products of each, alternating, best of five
-// (SSP_CSR_VARIANT=0/1 forces one).  The row form is kept unless the staged
-// form is faster by more than 10 %, so that timing noise (a profiler's
-// per-dispatch overhead, for instance) cannot flip the choice between runs.
+// The three CSR kernel forms give bitwise-identical products; pick one for
+// this matrix by timing four back-to-back products of each, alternating,
+// best of three (SSP_CSR_VARIANT=0/1/2 forces one).  Preference order sliced ELL, row,
+// staged: a later form is taken only if it is faster by more than 10 %, so
+// that timing noise (a profiler's per-dispatch overhead, for instance)
+// cannot flip the choice between runs.
 int csr_pick_variant(ssp_handle *h, ssp_matrix *A) {
   const char *env = getenv("SSP_CSR_VARIANT");
-  if (env && (env[0] == '0' || env[0] == '1')) {
+  if (env && env[0] >= '0' && env[0] <= '2' && (env[0] != '2' || A->sell_col)) {
     A->csr.variant = env[0] - '0';
     return SSP_OK;
   }
@@ -238,28 +252,84 @@ int csr_pick_variant(ssp_handle *h, ssp_matrix *A) {
   hipEvent_t e0, e1;
   HIPCHK(h, hipEventCreate(&e0));
   HIPCHK(h, hipEventCreate(&e1));
-  float best[2] = {1e30f, 1e30f};
-  for (int v = CSR_STAGED; v <= CSR_ROW && rc == SSP_OK; ++v) {   // warm-up
+  const int nv = A->sell_col ? 3 : 2;
+  float best[3] = {1e30f, 1e30f, 1e30f};
+  for (int v = 0; v < nv && rc == SSP_OK; ++v) {   // warm-up
     A->csr.variant = v;
     rc = launch_op<double>(h, A, xv, EpiStore<double>{y}, 0);
   }
-  for (int rep = 0; rep < 5 && rc == SSP_OK; ++rep)
-    for (int v = CSR_STAGED; v <= CSR_ROW && rc == SSP_OK; ++v) {
+  for (int rep = 0; rep < 3 && rc == SSP_OK; ++rep)
+    for (int v = 0; v < nv && rc == SSP_OK; ++v) {
       A->csr.variant = v;
       (void)hipEventRecord(e0, h->stream);
-      rc = launch_op<double>(h, A, xv, EpiStore<double>{y}, 0);
+      for (int q = 0; q < 4 && rc == SSP_OK; ++q)
+        rc = launch_op<double>(h, A, xv, EpiStore<double>{y}, 0);
       (void)hipEventRecord(e1, h->stream);
       (void)hipEventSynchronize(e1);
       float ms = 0.f;
       (void)hipEventElapsedTime(&ms, e0, e1);
       if (ms < best[v]) best[v] = ms;
     }
-  A->csr.variant = (best[CSR_STAGED] < 0.9f * best[CSR_ROW]) ? CSR_STAGED : CSR_ROW;
+  int pick = (nv == 3) ? CSR_SELL : CSR_ROW;
+  if (nv == 3 && best[CSR_ROW] < 0.9f * best[pick]) pick = CSR_ROW;
+  if (best[CSR_STAGED] < 0.9f * best[pick]) pick = CSR_STAGED;
+  A->csr.variant = pick;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipFree(y);
   (void)hipFree(xv);
   return rc;
+}
+
+// Sliced ELL copy of a CSR matrix (slices of 64 rows, padded to the longest
+// row of each slice).  Skipped (the form is then not offered) when padding
+// would more than double the stored entries.
+int csr_build_sell(ssp_handle *h, ssp_matrix *A) {
+  const int64_t ns = (A->n + kWave - 1) / kWave;
+  int32_t *w = nullptr;
+  HIPCHK(h, hipMalloc(&w, sizeof(int32_t) * ns));
+  k_sell_width<<<(unsigned)((ns + kWG - 1) / kWG), kWG, 0, h->stream>>>(A->n, ns, A->csr.rowptr,
+                                                                        w);
+  LAUNCHCHK(h);
+  std::vector<int32_t> hw(ns);
+  std::vector<int64_t> off(ns);
+  HIPCHK(h, hipMemcpyAsync(hw.data(), w, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  int64_t tot = 0;
+  for (int64_t i = 0; i < ns; ++i) {
+    off[i] = tot;
+    tot += (int64_t)kWave * hw[i];
+  }
+  if (tot > 2 * std::max<int64_t>(A->nnz, 1) + kWave) {
+    (void)hipFree(w);
+    return SSP_OK;
+  }
+  const int64_t alloc = std::max<int64_t>(tot, 1);
+  if (hipMalloc(&A->slice_off, sizeof(int64_t) * ns) != hipSuccess ||
+      hipMalloc(&A->sell_col, sizeof(int32_t) * alloc) != hipSuccess ||
+      hipMalloc(&A->sell_val, sizeof(double) * alloc) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipFree(w);
+    hfree_t(A->slice_off);
+    hfree_t(A->sell_col);
+    hfree_t(A->sell_val);
+    return SSP_OK;   // the form is optional
+  }
+  A->slice_w = w;
+  A->sell_entries = tot;
+  HIPCHK(h, hipMemcpyAsync(A->slice_off, off.data(), sizeof(int64_t) * ns, hipMemcpyHostToDevice,
+                           h->stream));
+  k_sell_fill<<<(unsigned)((ns * kWave + kWG - 1) / kWG), kWG, 0, h->stream>>>(
+      A->n, ns, A->csr.rowptr, A->csr.colind, A->csr.val, A->slice_off, A->slice_w, A->sell_col,
+      A->sell_val);
+  LAUNCHCHK(h);
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  A->csr.sell_col = A->sell_col;
+  A->csr.sell_val = A->sell_val;
+  A->csr.slice_off = A->slice_off;
+  A->csr.slice_w = A->slice_w;
+  A->csr.nslices = ns;
+  return SSP_OK;
 }
 
 int csr_finish_setup(ssp_handle *h, ssp_matrix *A) {
@@ -300,6 +370,8 @@ int csr_finish_setup(ssp_handle *h, ssp_matrix *A) {
     (void)hipFree(A->dinv);
     A->dinv = nullptr;
   }
+  const int rc = csr_build_sell(h, A);
+  if (rc) return rc;
   return csr_pick_variant(h, A);
 }
 
@@ -804,6 +876,12 @@ int ssp_matrix_csr_arrays(const ssp_matrix *A, const int32_t **rowptr, const int
   return SSP_OK;
 }
 
+int ssp_matrix_csr_form(const ssp_matrix *A, int *form) {
+  if (!A || !form) return SSP_EINVAL;
+  *form = A->kind == 0 ? A->csr.variant : -1;
+  return SSP_OK;
+}
+
 int ssp_matrix_destroy(ssp_matrix *A) {
   if (!A) return SSP_OK;
   if (A->h) {
@@ -814,6 +892,11 @@ int ssp_matrix_destroy(ssp_matrix *A) {
   hfree_t(A->own_colind);
   hfree_t(A->own_val);
   hfree_t(A->val32);
+  hfree_t(A->sell_col);
+  hfree_t(A->sell_val);
+  hfree_t(A->sell_val32);
+  hfree_t(A->slice_off);
+  hfree_t(A->slice_w);
   hfree_t(A->k32);
   hfree_t(A->dinv);
   hfree_t(A->dinv32);

@@ -73,6 +73,12 @@ struct ssp_matrix {
   int32_t *own_rowptr = nullptr, *own_colind = nullptr;
   double *own_val = nullptr;
   float *val32 = nullptr;
+  int32_t *sell_col = nullptr;     // sliced ELL copy (library-owned)
+  double *sell_val = nullptr;
+  float *sell_val32 = nullptr;
+  int64_t *slice_off = nullptr;
+  int32_t *slice_w = nullptr;
+  int64_t sell_entries = 0;
   ssp::StencilArgs<double> sten{};
   ssp::StencilArgs<float> sten32{};
   float *k32 = nullptr;
@@ -134,6 +140,11 @@ inline bool tiled_of(const ssp_matrix *A, Tiling3 &t) {
 inline int grid_of(const ssp_matrix *A) {
   Tiling3 t;
   if (tiled_of(A, t)) return t.ntx * t.nty * t.ntz;
+  if (A->kind == 0 && A->csr.variant == CSR_SELL) {
+    int64_t g = (A->csr.nslices + kWG / kWave - 1) / (kWG / kWave);
+    if (g > kGridMax) g = kGridMax;
+    return (int)std::max<int64_t>(g, 1);
+  }
   if (A->kind == 0 && A->csr.variant == CSR_STAGED) {
     int64_t g = A->csr.nrb;
     if (g > kGridMax) g = kGridMax;
@@ -195,6 +206,9 @@ int launch_op(ssp_handle *h, const ssp_matrix *A, const T *x, const Epi &epi, in
       if (A->csr.variant == CSR_ROW)
         k_csr<CSR_ROW, T, Epi><<<G, kWG, 0, h->stream>>>(csr_of(A, tag), x, xs, epi, h->st,
                                                           h->ws.partials);
+      else if (A->csr.variant == CSR_SELL)
+        k_csr<CSR_SELL, T, Epi><<<G, kWG, 0, h->stream>>>(csr_of(A, tag), x, xs, epi, h->st,
+                                                           h->ws.partials);
       else
         k_csr<CSR_STAGED, T, Epi><<<G, kWG, 0, h->stream>>>(csr_of(A, tag), x, xs, epi, h->st,
                                                              h->ws.partials);

@@ -12,7 +12,7 @@
 
 namespace ssp {
 
-enum : int { CSR_STAGED = 0, CSR_ROW = 1 };
+enum : int { CSR_STAGED = 0, CSR_ROW = 1, CSR_SELL = 2 };
 enum : int { K_2D5 = 1, K_3D7 = 2, K_3D27 = 3, K_VARK = 4 };
 
 template <typename T>
@@ -23,7 +23,15 @@ struct CsrArgs {
   const T *val;
   int rows_per_rb;   // rows per LDS row block (CSR_STAGED, <= kCsrRowsMax)
   int64_t nrb;       // number of row blocks
-  int variant;       // CSR_STAGED or CSR_ROW, chosen per matrix by timing
+  int variant;       // CSR_STAGED, CSR_ROW or CSR_SELL, chosen per matrix by timing
+  // sliced ELL copy (CSR_SELL): slice sl holds rows 64 sl .. 64 sl + 63; entry
+  // u of its row `lane` is at slice_off[sl] + 64 u + lane, u < slice_w[sl];
+  // entries past a row's end have column -1 and value 0
+  const int32_t *sell_col;
+  const T *sell_val;
+  const int64_t *slice_off;
+  const int32_t *slice_w;
+  int64_t nslices;
 };
 
 template <typename T>
@@ -171,6 +179,53 @@ __device__ __forceinline__ void csr_rows_direct(const CsrArgs<T> &A, const T *__
       [&](int64_t i, T v, const NoPre &) { f(i, v); });
 }
 
+// Sliced ELL form: each wavefront takes whole slices of 64 rows (one row per
+// lane); the slice width is uniform across the wavefront, so the loop has no
+// divergence, and entry u of the 64 rows is one coalesced load of the
+// column indices and one of the values, independent of any row pointer.
+// Padded entries (column -1) are masked out of the sum: each row's sum has
+// the same terms, order and rounding as the CSR product.
+template <typename T, class Pre, class F>
+__device__ __forceinline__ void sell_rows(const CsrArgs<T> &A, const T *__restrict__ x, Pre &&pre,
+                                          F &&f, T xs) {
+#pragma clang fp contract(off)
+  constexpr int U = 8;
+  int64_t s0, s1;
+  block_chunk(A.nslices, logical_block(), gridDim.x, s0, s1);
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  for (int64_t sl = s0 + wave; sl < s1; sl += kWG / kWave) {
+    const int64_t row = sl * kWave + lane;
+    const bool live = row < A.n;
+    const int64_t rowc = live ? row : A.n - 1;
+    const int64_t off = A.slice_off[sl];
+    const int w = A.slice_w[sl];
+    const auto p = pre(rowc);
+    T acc = 0;
+    for (int u0 = 0; u0 < w; u0 += U) {
+      int ci[U];
+      T vv[U];
+      bool ok[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int uu = (u0 + u < w) ? u0 + u : w - 1;
+        const int64_t e = off + (int64_t)uu * kWave + lane;
+        const int c = A.sell_col[e];
+        ok[u] = (u0 + u < w) && c >= 0;
+        ci[u] = c >= 0 ? c : (int)rowc;
+        vv[u] = A.sell_val[e];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) vv[u] = vv[u] * (xs * x[ci[u]]);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const T t = acc + vv[u];
+        acc = ok[u] ? t : acc;
+      }
+    }
+    if (live) f(row, acc, p);
+  }
+}
+
 // The workgroup's share of a whole-matrix product (contiguous chunk).  The
 // kernel form is a template parameter, so the row form carries neither the
 // staging buffer nor its registers (occupancy).
@@ -181,6 +236,8 @@ __device__ __forceinline__ void csr_rows(const CsrArgs<T> &A, const T *__restric
     int64_t r0, r1;
     block_chunk(A.n, logical_block(), gridDim.x, r0, r1);
     csr_rows_direct(A, x, r0, r1, pre, f, xs);
+  } else if constexpr (VARIANT == CSR_SELL) {
+    sell_rows(A, x, pre, f, xs);
   } else {
     int64_t rb0, rb1;
     block_chunk(A.nrb, logical_block(), gridDim.x, rb0, rb1);

@@ -152,4 +152,47 @@ __global__ __launch_bounds__(kWG) void k_csr_validate(int64_t n, int64_t nnz,
   if (!ok) atomicOr(bad, 1);
 }
 
+// Sliced ELL set-up: the width of slice sl is its longest row.
+__global__ __launch_bounds__(kWG) void k_sell_width(int64_t n, int64_t nslices,
+                                                    const int32_t *__restrict__ rowptr,
+                                                    int32_t *__restrict__ width) {
+  const int64_t sl = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (sl >= nslices) return;
+  int w = 0;
+  for (int l = 0; l < kWave; ++l) {
+    const int64_t r = sl * kWave + l;
+    if (r < n) w = max(w, rowptr[r + 1] - rowptr[r]);
+  }
+  width[sl] = w;
+}
+
+// One thread per (padded) row: its entries in slice order, then padding
+// (column -1, value 0) up to the slice width.
+__global__ __launch_bounds__(kWG) void k_sell_fill(int64_t n, int64_t nslices,
+                                                   const int32_t *__restrict__ rowptr,
+                                                   const int32_t *__restrict__ colind,
+                                                   const double *__restrict__ val,
+                                                   const int64_t *__restrict__ slice_off,
+                                                   const int32_t *__restrict__ width,
+                                                   int32_t *__restrict__ scol,
+                                                   double *__restrict__ sval) {
+  const int64_t r = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (r >= nslices * kWave) return;
+  const int64_t sl = r / kWave;
+  const int lane = (int)(r - sl * kWave);
+  const int w = width[sl];
+  const int a = r < n ? rowptr[r] : 0;
+  const int len = r < n ? rowptr[r + 1] - a : 0;
+  for (int u = 0; u < w; ++u) {
+    const int64_t e = slice_off[sl] + (int64_t)u * kWave + lane;
+    if (u < len) {
+      scol[e] = colind[a + u];
+      sval[e] = val[a + u];
+    } else {
+      scol[e] = -1;
+      sval[e] = 0.0;
+    }
+  }
+}
+
 }  // namespace ssp

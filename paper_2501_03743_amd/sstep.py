@@ -39,7 +39,7 @@ EXPORTS = (
     "ssp_net_forward", "ssp_net_zero_grad", "ssp_net_backward", "ssp_net_loss",
     "ssp_net_adam_step", "ssp_net_get_state", "ssp_net_set_state", "ssp_conv3d",
     "ssp_conv3d_wgrad", "ssp_net_mfma_selftest", "ssp_get_warm_start",
-    "ssp_net_loss_h1",
+    "ssp_net_loss_h1", "ssp_matrix_csr_form",
 )
 
 
@@ -101,6 +101,7 @@ def load():
         "ssp_matrix_info": (i32, [vp, C.POINTER(i64), C.POINTER(i64)]),
         "ssp_matrix_csr_arrays": (i32, [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp)]),
         "ssp_matrix_destroy": (i32, [vp]),
+        "ssp_matrix_csr_form": (i32, [vp, C.POINTER(i32)]),
         "ssp_set_preconditioner": (i32, [vp, i32]),
         "ssp_spmv": (i32, [vp, vp, vp, vp]),
         "ssp_mpk": (i32, [vp, vp, vp, i32, vp, i64, vp]),
@@ -183,6 +184,13 @@ class Matrix:
         self.nnz = nnz
         self._keep = keep       # tensors the library borrows
         handle._matrices.add(self)
+
+    @property
+    def csr_form(self) -> int:
+        """CSR kernel form in use (0 staged, 1 row, 2 sliced ELL; -1 matrix-free)."""
+        f = C.c_int()
+        load().ssp_matrix_csr_form(self._p, C.byref(f))
+        return f.value
 
     def set_preconditioner(self, kind: str):
         rc = load().ssp_set_preconditioner(self._p, PREC[kind])

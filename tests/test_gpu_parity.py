@@ -286,3 +286,31 @@ def test_paper_iteration_count_250cubed(H):
         print("250^3 s=%d CG-equivalent iterations:" % s, r2.cg_equiv)
         assert r2.status == 0 and abs(r2.cg_equiv - r.outer) <= 2 * s, (s, r2.cg_equiv)
     A.close()
+
+
+@pytest.mark.parametrize("variant", ["0", "1", "2"])
+@pytest.mark.parametrize("kind,shape", [("3d7", (33, 20, 21)), ("3d27", (13, 11, 9)),
+                                        ("3d7_vark", (17, 9, 70))])
+def test_each_csr_form_bitexact(H, monkeypatch, kind, shape, variant):
+    """Every CSR kernel form (LDS-staged, row per thread, sliced ELL) gives the
+    oracle's products bit for bit, and the same solve."""
+    monkeypatch.setenv("SSP_CSR_VARIANT", variant)
+    k = np.exp(wl.gaussian_random_field(shape, 0.5, 0.1, 3)) if kind == "3d7_vark" else None
+    csr = oracle.stencil_csr(kind, shape, k=k)
+    A = H.matrix_csr(*[torch.from_numpy(a).cuda() for a in csr], flags=2)
+    op = oracle.Operator("csr", csr=csr)
+    n = len(csr[0]) - 1
+    x = wl.normal_rhs(n, 11)
+    y = torch.full((n,), np.nan, dtype=torch.float64, device="cuda")
+    H.spmv(A, dev(x), y)
+    assert np.array_equal(host(y), op.apply(x))
+    P, vm = H.mpk(A, dev(x), 3)
+    Pref, vmref = oracle.mpk_cvm(op, x, 3)
+    assert np.array_equal(host(P), Pref)
+    b = wl.normal_rhs(n, 12)
+    xs = torch.zeros(n, dtype=torch.float64, device="cuda")
+    r = H.solve(A, dev(b), xs, s=4, rtol=1e-8)
+    ref = oracle.sstep(op, b, 4, rtol=1e-8)
+    assert r.status == 0 and abs(r.outer - ref.outer) <= 2
+    assert _rel(host(xs), ref.x) <= 1e-9
+    A.close()
