@@ -159,6 +159,119 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const bf16 *__restrict__ in, 
   }
 }
 
+// Stride-1 convolutions (and their input gradients) with the input tile in
+// LDS: a workgroup computes a CTZ x CTY x CTX block of output points (eight
+// 16-point rows along x, two per wavefront) and first stages the block plus
+// a one-cell halo, all channels, in LDS (zero outside the grid).  Each input
+// value then serves all 27 taps from LDS instead of being gathered from the
+// caches 27 times; the weight fragment of a k chunk is loaded once per
+// wavefront and used for both of its rows.  Same operands, same k order and
+// same matrix-core sequence per output as k_conv_mfma, so the results are
+// identical.  MODE 1 reads the taps mirrored (q = p - o).  Dynamic LDS:
+// (CTZ+2)(CTY+2)(CTX+2) * cin BF16 values.
+constexpr int CTX = 16, CTY = 4, CTZ = 2;
+template <int MODE, int NS>
+__global__ __launch_bounds__(256) void k_conv_tiled(const bf16 *__restrict__ in, int cin, Grid3 g,
+                                                    const bf16 *__restrict__ wt, int kp,
+                                                    const float *__restrict__ bias, int relu,
+                                                    float *__restrict__ out_f,
+                                                    bf16 *__restrict__ out_b) {
+  constexpr int HX = CTX + 2, HY = CTY + 2, HZ = CTZ + 2;
+  extern __shared__ __align__(16) bf16 s_in[];
+  __shared__ int s_tap[512];
+  __shared__ int s_ci[512];
+  const int nk8 = kp / 8;
+  for (int i = threadIdx.x; i < nk8; i += 256) {
+    const int k = i * 8;
+    const int t = k / cin;
+    s_tap[i] = t;
+    s_ci[i] = k - t * cin;
+  }
+  const int ntx = (g.W + CTX - 1) / CTX, nty = (g.H + CTY - 1) / CTY, ntz = (g.D + CTZ - 1) / CTZ;
+  int64_t bi = blockIdx.x;
+  const int tx = (int)(bi % ntx);
+  bi /= ntx;
+  const int ty = (int)(bi % nty);
+  bi /= nty;
+  const int tz = (int)(bi % ntz);
+  const int b = (int)(bi / ntz);
+  const int x0 = tx * CTX, y0 = ty * CTY, z0 = tz * CTZ;
+  const int ng = cin / 8;
+  const bf16x8 zero8 = {};
+  for (int e = threadIdx.x; e < HZ * HY * HX * ng; e += 256) {
+    const int pi = e / ng, cg = e - pi * ng;
+    const int hx = pi % HX, hy = (pi / HX) % HY, hz = pi / (HX * HY);
+    const int qx = x0 + hx - 1, qy = y0 + hy - 1, qz = z0 + hz - 1;
+    bf16x8 v = zero8;
+    if (qx >= 0 && qx < g.W && qy >= 0 && qy < g.H && qz >= 0 && qz < g.D)
+      v = *(const bf16x8 *)(in + encode(b, qz, qy, qx, g) * cin + cg * 8);
+    *(bf16x8 *)(s_in + (int64_t)pi * cin + cg * 8) = v;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  const int m = lane % 16, gq = lane / 16;
+  int rz[2], ry[2];
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt) {
+    const int r = wave * 2 + mt;   // 0..7: (z, y) row of the block
+    rz[mt] = r / CTY;
+    ry[mt] = r % CTY;
+  }
+  f32x4 acc[2][NS];
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int n = 0; n < NS; ++n) acc[mt][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int kc = 0; kc < kp; kc += 32) {
+    const int i8 = (kc >> 3) + gq;
+    const int t = s_tap[i8];
+    bf16x8 a[2] = {zero8, zero8};
+    if (t < 27) {
+      int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+      if (MODE == 1) {
+        dz = -dz;
+        dy = -dy;
+        dx = -dx;
+      }
+      const int c0 = s_ci[i8];
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) {
+        const int pi = ((rz[mt] + 1 + dz) * HY + (ry[mt] + 1 + dy)) * HX + (m + 1 + dx);
+        a[mt] = *(const bf16x8 *)(s_in + (int64_t)pi * cin + c0);
+      }
+    }
+#pragma unroll
+    for (int n = 0; n < NS; ++n) {
+      const bf16x8 w = *(const bf16x8 *)(wt + (int64_t)(n * 16 + m) * kp + kc + gq * 8);
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+        acc[mt][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], w, acc[mt][n], 0, 0, 0);
+    }
+  }
+  const int cout = NS * 16;
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt) {
+    const int z = z0 + rz[mt], y = y0 + ry[mt];
+    if (z >= g.D || y >= g.H) continue;
+#pragma unroll
+    for (int n = 0; n < NS; ++n) {
+      const int c = n * 16 + m;
+      const float bs = bias ? bias[c] : 0.0f;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int x = x0 + 4 * gq + i;
+        if (x < g.W) {
+          const int64_t po = encode(b, z, y, x, g);
+          float v = acc[mt][n][i] + bs;
+          if (relu) v = v > 0.0f ? v : 0.0f;
+          if (out_f) out_f[po * cout + c] = v;
+          if (out_b) out_b[po * cout + c] = (bf16)v;
+        }
+      }
+    }
+  }
+}
+
 // Weight and bias gradients of one tap on the matrix cores: a GEMM with
 // M = ci, N = co and K = the block's output points,
 //   part[blk][t][ci][co] = sum_p x[q_t(p), ci] dz[p, co].
@@ -549,6 +662,21 @@ template <int MODE>
 int launch_conv(ssp_handle *h, const bf16 *in, int cin, Grid3 gi, Grid3 go, int stride,
                 const bf16 *wt, int kp, const float *bias, int relu, float *out_f, bf16 *out_b,
                 int cout) {
+  if (stride == 1 && cin <= 64) {
+    // LDS-staged input tile (same results, far fewer cache gathers)
+    const unsigned tiles = (unsigned)(((gi.W + CTX - 1) / CTX) * ((gi.H + CTY - 1) / CTY) *
+                                      ((gi.D + CTZ - 1) / CTZ) * gi.B);
+    const size_t lds = sizeof(bf16) * (CTZ + 2) * (CTY + 2) * (CTX + 2) * cin;
+    switch (cout / 16) {
+      case 1: k_conv_tiled<MODE, 1><<<tiles, 256, lds, h->stream>>>(in, cin, gi, wt, kp, bias, relu, out_f, out_b); break;
+      case 2: k_conv_tiled<MODE, 2><<<tiles, 256, lds, h->stream>>>(in, cin, gi, wt, kp, bias, relu, out_f, out_b); break;
+      case 3: k_conv_tiled<MODE, 3><<<tiles, 256, lds, h->stream>>>(in, cin, gi, wt, kp, bias, relu, out_f, out_b); break;
+      case 4: k_conv_tiled<MODE, 4><<<tiles, 256, lds, h->stream>>>(in, cin, gi, wt, kp, bias, relu, out_f, out_b); break;
+      default: return fail(h, SSP_EINVAL, "conv: unsupported channel count");
+    }
+    LAUNCHCHK(h);
+    return SSP_OK;
+  }
   const unsigned grid = (unsigned)((go.points() + 63) / 64);
   switch (cout / 16) {
     case 1: k_conv_mfma<MODE, 1><<<grid, 256, 0, h->stream>>>(in, cin, gi, go, stride, wt, kp, bias, relu, out_f, out_b); break;
