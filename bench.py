@@ -507,7 +507,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "3D 7-point Poisson 128^3 (n=2097152, nnz=%d), FP64 CSR, Jacobi, "
                                "s=4, b~N(0,1) seed 0, x0=0, rtol 1e-8" % nnz,
-                   "global_batch": 1, "seq_len": None, "parallelism": "none (1 GPU)"},
+                   "method": "preconditioned s-step CG (Chronopoulos-Gear), s=4",
+                   "csr_kernel_form": A.csr_form, "parallelism": "none (1 GPU)"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "matrix-powers CSR SpMV + Jacobi (power j < s)",
