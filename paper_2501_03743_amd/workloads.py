@@ -214,3 +214,70 @@ def warm_start_problem(shape, seed: int, sigma: float = 1.0, ell: float = 0.1, d
     f = fourier_source_device(shape, 2 * seed + 1, device=device)
     h = 1.0 / (max(nx, ny, nz) + 1)
     return logk, torch.exp(logk), f, f * (h * h)
+
+
+def random_graph_laplacian(n: int, seed: int, mean_degree: float = 6.0, hub_fraction: float = 0.01,
+                           hub_degree: int = 60):
+    """CSR (rowptr, colind, val) of L + I for a random undirected graph: most
+    vertices get ~mean_degree random neighbours, a few hubs many more, so row
+    lengths are irregular (1 to ~hub_degree + 1).  SPD (diagonally dominant)."""
+    g = rng(seed)
+    m = int(n * mean_degree / 2)
+    src = g.integers(0, n, size=m)
+    dst = g.integers(0, n, size=m)
+    hubs = g.choice(n, size=max(1, int(n * hub_fraction)), replace=False)
+    hs = np.repeat(hubs, hub_degree)
+    hd = g.integers(0, n, size=hs.size)
+    src = np.concatenate([src, hs])
+    dst = np.concatenate([dst, hd])
+    keep = src != dst
+    src, dst = src[keep], dst[keep]
+    a = np.concatenate([src, dst])
+    b = np.concatenate([dst, src])
+    key = np.unique(a.astype(np.int64) * n + b)
+    rows, cols = key // n, key % n
+    w = np.full(rows.size, -1.0)
+    deg = np.bincount(rows, minlength=n).astype(np.float64)
+    rows = np.concatenate([rows, np.arange(n)])
+    cols = np.concatenate([cols, np.arange(n)])
+    vals = np.concatenate([w, deg + 1.0])
+    order = np.lexsort((cols, rows))
+    rows, cols, vals = rows[order], cols[order], vals[order]
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=n), out=rowptr[1:])
+    return rowptr.astype(np.int32), cols.astype(np.int32), vals
+
+
+def stencil_with_long_rows(shape, seed: int, every: int = 4, extra: int = 10):
+    """The 3D 7-point CSR matrix plus, in one row of every `every`-th block of
+    64 rows, `extra` symmetric long-range couplings (-0.05, diagonals raised
+    to keep diagonal dominance): SPD, with a few rows longer than the 8-entry
+    load chunk in otherwise regular slices."""
+    rp, ci, va = stencil_csr("3d7", shape)
+    n = len(rp) - 1
+    g = rng(seed)
+    rows = np.repeat(np.arange(n), np.diff(rp)).astype(np.int64)
+    cols = ci.astype(np.int64)
+    vals = va.copy()
+    add_r, add_c = [], []
+    for sl in range(0, (n + 63) // 64, every):
+        r = min(sl * 64 + int(g.integers(0, 64)), n - 1)
+        cand = g.choice(n, size=extra * 3, replace=False)
+        cand = [int(c) for c in cand if abs(int(c) - r) > 1][:extra]
+        for c in cand:
+            add_r += [r, c]
+            add_c += [c, r]
+    key_old = rows * n + cols
+    key_new = np.array(add_r, dtype=np.int64) * n + np.array(add_c, dtype=np.int64)
+    key_new = np.setdiff1d(np.unique(key_new), key_old)
+    nr, nc = key_new // n, key_new % n
+    diag_add = np.bincount(nr, minlength=n) * 0.05
+    rows = np.concatenate([rows, nr])
+    cols = np.concatenate([cols, nc])
+    vals = np.concatenate([vals, np.full(nr.size, -0.05)])
+    vals[rows == cols] += diag_add[rows[rows == cols]]
+    order = np.lexsort((cols, rows))
+    rows, cols, vals = rows[order], cols[order], vals[order]
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=n), out=rowptr[1:])
+    return rowptr.astype(np.int32), cols.astype(np.int32), vals

@@ -314,3 +314,59 @@ def test_each_csr_form_bitexact(H, monkeypatch, kind, shape, variant):
     assert r.status == 0 and abs(r.outer - ref.outer) <= 2
     assert _rel(host(xs), ref.x) <= 1e-9
     A.close()
+
+
+@pytest.mark.parametrize("variant", ["0", "1", "2"])
+@pytest.mark.parametrize("matrix", ["graph", "long_rows"])
+def test_irregular_rows_every_csr_form(H, monkeypatch, variant, matrix):
+    """Irregular row lengths through every CSR form: a random graph Laplacian
+    (1 to ~70 entries per row; too irregular for the sliced copy, which is
+    then not built) and a stencil with a few 18-entry rows (sliced copy
+    built, rows longer than the 8-entry load chunk).  Products bit for bit,
+    and the solve against the oracle."""
+    monkeypatch.setenv("SSP_CSR_VARIANT", variant)
+    if matrix == "graph":
+        csr = wl.random_graph_laplacian(6000, 3)
+    else:
+        csr = wl.stencil_with_long_rows((30, 30, 30), 2)
+    A = H.matrix_csr(*[torch.from_numpy(a).cuda() for a in csr], flags=2)
+    if matrix == "long_rows" or variant != "2":
+        assert A.csr_form == int(variant)
+    op = oracle.Operator("csr", csr=csr)
+    n = len(csr[0]) - 1
+    x = wl.normal_rhs(n, 21)
+    y = torch.full((n,), np.nan, dtype=torch.float64, device="cuda")
+    H.spmv(A, dev(x), y)
+    assert np.array_equal(host(y), op.apply(x))
+    P, vm = H.mpk(A, dev(x), 4)
+    Pref, vmref = oracle.mpk_cvm(op, x, 4)
+    assert np.array_equal(host(P), Pref)
+    xs = torch.zeros(n, dtype=torch.float64, device="cuda")
+    r = H.solve(A, dev(x), xs, s=4, rtol=1e-8)
+    ref = oracle.sstep(op, x, 4, rtol=1e-8)
+    assert r.status == 0 and abs(r.outer - ref.outer) <= 2, (r.outer, ref.outer)
+    assert _rel(host(xs), ref.x) <= 1e-9
+    A.close()
+
+
+@pytest.mark.parametrize("variant", ["0", "1", "2"])
+def test_empty_rows_every_csr_form(H, monkeypatch, variant):
+    """Rows with no stored entry give 0 in every form."""
+    monkeypatch.setenv("SSP_CSR_VARIANT", variant)
+    rp, ci, va = wl.random_graph_laplacian(3000, 4)
+    lens = np.diff(rp)
+    drop = np.zeros(len(lens), dtype=bool)
+    drop[::7] = True                     # empty every 7th row
+    keep = ~np.repeat(drop, lens)
+    ci2, va2 = ci[keep], va[keep]
+    rp2 = np.zeros_like(rp)
+    np.cumsum(np.where(drop, 0, lens), out=rp2[1:])
+    A = H.matrix_csr(*[torch.from_numpy(a).cuda() for a in (rp2, ci2, va2)], flags=1)
+    op = oracle.Operator("csr", csr=(rp2, ci2, va2))
+    x = wl.normal_rhs(len(rp2) - 1, 5)
+    y = torch.full((len(x),), np.nan, dtype=torch.float64, device="cuda")
+    H.spmv(A, dev(x), y)
+    got = host(y)
+    assert np.array_equal(got, op.apply(x))
+    assert np.all(got[::7] == 0.0)
+    A.close()
