@@ -184,7 +184,7 @@ def bench_batch(H, count=32, lo=32, hi=160, seed=0):
     return out
 
 
-def bench_warmstart(H, n_train=2000, n_eval=200, side=96, epochs=24, lr=2e-3, batch=4,
+def bench_warmstart(H, n_train=2000, n_eval=200, side=96, epochs=40, lr=2e-3, batch=4,
                     log=None, sweeps=16):
     """The learned warm start on -div(k grad u) = f at side^3: log k a Gaussian
     random field (sigma 1, correlation length 0.1), f a random sum of 16
@@ -208,6 +208,9 @@ def bench_warmstart(H, n_train=2000, n_eval=200, side=96, epochs=24, lr=2e-3, ba
     seeds = list(range(20000, 20000 + n_eval))
     rec = ws.evaluate(H, model, seeds, s=S, rtol=RTOL, sweeps=sweeps)
     summ = ws.summarize(rec)
+    # the same held-out seeds at a looser tolerance, where a guess's share of
+    # the decades CG must gain is larger
+    summ_1e6 = ws.summarize(ws.evaluate(H, model, seeds[:50], s=S, rtol=1e-6, sweeps=sweeps))
     # the full forms at equal final accuracy on the first held-out seeds
     forms = {}
     m = min(20, n_eval)
@@ -245,7 +248,7 @@ def bench_warmstart(H, n_train=2000, n_eval=200, side=96, epochs=24, lr=2e-3, ba
         "loss": "energy e^T (L + 1e-3 I) e", "smoothing_sweeps": sweeps,
         "generate_s": gen_s, "train_s": train_s, "loss_first": hist[0], "loss_last": hist[-1],
         "params": params,
-        "held_out": summ, "forms_first_%d" % m: forms,
+        "held_out": summ, "held_out_rtol_1e-6_first_50": summ_1e6, "forms_first_%d" % m: forms,
     }
 
 
@@ -266,7 +269,7 @@ def main():
     ap.add_argument("--ws-train", type=int, default=2000)
     ap.add_argument("--ws-eval", type=int, default=200)
     ap.add_argument("--ws-side", type=int, default=96)
-    ap.add_argument("--ws-epochs", type=int, default=24)
+    ap.add_argument("--ws-epochs", type=int, default=40)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only a plain 1 GiB device-to-device copy, three times (the "
                          "reference for the FETCH_SIZE / WRITE_SIZE counter scale)")
