@@ -172,6 +172,7 @@ int ssp_solve_batch(ssp_handle *h, int nsys, const ssp_matrix *const *A, const d
     y.n = l.n;
     y.tile_rows = l.tile_rows;
     y.ntiles = l.ntiles;
+    y.single = trq <= 0;
     DevState &c = hdr[i];
     memset(&c, 0, sizeof(c));
     c.status = ST_RUNNING;

@@ -51,7 +51,7 @@ struct BatchSys {
   int64_t n;
   int64_t tile_rows;
   int ntiles;
-  int pad;
+  int single;               // 1: the partition of a single solve (tile t = its block t)
 };
 
 // Per-system scheduling words (device atomics).
@@ -128,7 +128,17 @@ __device__ void batch_tile(const BatchSys &y, const BatchSched &sc, int t) {
   } else if (sc.phase == PH_UPDATE) {
     UpdateCoef<S, float> c;
     c.load(y.st);
-    double v[1] = {update_rows<S, float>(c, lo, hi, y.ld, Pc, Po, y.d32, y.r32, y.pc32, 0.0f)};
+    double v[1] = {0.0};
+    if (y.single) {
+      // the rows block t of the single solve's update kernel takes
+      const XcdSched xs = xcd_sched(y.n, kWG, y.ntiles, t);
+      for (int64_t b0 = xs.first; b0 < xs.end; b0 += xs.stride) {
+        const int64_t b1 = b0 + kWG < xs.end ? b0 + kWG : xs.end;
+        v[0] += update_rows<S, float>(c, b0, b1, y.ld, Pc, Po, y.d32, y.r32, y.pc32, 0.0f);
+      }
+    } else {
+      v[0] = update_rows<S, float>(c, lo, hi, y.ld, Pc, Po, y.d32, y.r32, y.pc32, 0.0f);
+    }
     block_store_sums<1>(v, y.partials + t, y.ntiles);
   } else if (sc.phase == PH_IRADD) {
     for (int64_t i = lo + threadIdx.x; i < hi; i += kWG) y.x[i] = y.x[i] + (double)y.d32[i];

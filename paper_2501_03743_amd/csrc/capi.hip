@@ -36,7 +36,9 @@ int ensure_fp32(ssp_handle *h, ssp_matrix *A) {
     A->csr32 = CsrArgs<float>{A->csr.n, A->csr.rowptr, A->csr.colind, A->val32,
                               A->csr.rows_per_rb, A->csr.nrb, A->csr.variant,
                               A->csr.sell_col, nullptr, A->csr.slice_off, A->csr.slice_w,
-                              A->csr.nslices};
+                              A->csr.nslices,
+                              A->sell_entries * (int64_t)(sizeof(float) + sizeof(int32_t)) >
+                                  kInfinityCache};
     if (A->sell_val) {
       const int64_t ne = A->sell_entries;
       if (hipMalloc(&A->sell_val32, sizeof(float) * ne) != hipSuccess) {
@@ -329,6 +331,7 @@ int csr_build_sell(ssp_handle *h, ssp_matrix *A) {
   A->csr.slice_off = A->slice_off;
   A->csr.slice_w = A->slice_w;
   A->csr.nslices = ns;
+  A->csr.sell_xcd = tot * (int64_t)(sizeof(double) + sizeof(int32_t)) > kInfinityCache;
   return SSP_OK;
 }
 

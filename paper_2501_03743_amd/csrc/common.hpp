@@ -11,6 +11,7 @@ constexpr int kSMax = 16;         // largest s (s x s moment matrices)
 constexpr int kWG = 256;          // threads per workgroup of every streaming kernel
 constexpr int kWave = 64;         // CDNA wavefront
 constexpr int kXcd = 8;           // MI355X: 8 accelerator dies, round-robin dispatch
+constexpr int64_t kInfinityCache = 256ll << 20;  // memory-side last-level cache (bytes)
 constexpr int kGridMax = 2048;    // workgroups of a streaming launch (8 per CU)
 constexpr int64_t kColumnStagger = 17 * 256;  // bytes added to block leading dimensions
 constexpr int kCsrLds = 4096;     // FP64 products staged in LDS per CSR row block
@@ -73,6 +74,38 @@ __device__ __forceinline__ void block_chunk(int64_t items, int lb, int G, int64_
   hi = lo + per;
   if (lo > items) lo = items;
   if (hi > items) hi = items;
+}
+
+// XCD-interleaved schedule of `items` for the calling workgroup.  The items
+// are split into kXcd contiguous ranges, one per XCD (the hardware deals
+// workgroups out round-robin over the XCDs), and each range is dealt out in
+// pieces of `piece` items to that XCD's workgroups in turn, so that at any
+// time an XCD's workgroups stream one compact region (HBM pages and the XCD's
+// L2 shared by neighbours) rather than one distant region each.  The
+// workgroup's pieces start at first, first + stride, ... below end.  Grids
+// smaller than kXcd take contiguous chunks.  G and b are the grid size and
+// the hardware block index (a batch tile passes the grid of the single solve
+// it reproduces and its tile index).
+struct XcdSched {
+  int64_t first, stride, end;
+};
+__device__ __forceinline__ XcdSched xcd_sched(int64_t items, int64_t piece, int G, int b) {
+  XcdSched s;
+  int64_t lo, hi;
+  if (G < kXcd) {
+    block_chunk(items, b, G, lo, hi);
+    s.first = lo;
+    s.stride = piece;
+  } else {
+    const int q = G / kXcd, rem = G % kXcd;
+    const int xcd = b % kXcd, local = b / kXcd;
+    const int qx = xcd < rem ? q + 1 : q;
+    block_chunk(items, xcd, kXcd, lo, hi);
+    s.first = lo + (int64_t)local * piece;
+    s.stride = (int64_t)qx * piece;
+  }
+  s.end = hi;
+  return s;
 }
 
 __device__ __forceinline__ double wave_sum(double v) {

@@ -557,6 +557,8 @@ __device__ __forceinline__ double update_rows(const UpdateCoef<S, T> &c, int64_t
   return part;
 }
 
+// The rows are dealt out in XCD-interleaved pieces of kWG (one row per
+// thread per piece); the partial is stored at the hardware block index.
 template <int S, typename T>
 __global__ __launch_bounds__(kWG) void k_update(int64_t n, int64_t ld, T *__restrict__ Pc,
                                                 T *__restrict__ Po, T *__restrict__ x,
@@ -565,10 +567,14 @@ __global__ __launch_bounds__(kWG) void k_update(int64_t n, int64_t ld, T *__rest
   if (st->status != ST_RUNNING) return;
   UpdateCoef<S, T> c;
   c.load(st);
-  int64_t lo, hi;
-  block_chunk(n, logical_block(), gridDim.x, lo, hi);
-  double v[1] = {update_rows<S, T>(c, lo, hi, ld, Pc, Po, x, r, pc, zc)};
-  block_store_sums<1>(v, partials + logical_block(), gridDim.x);
+  const XcdSched sc = xcd_sched(n, kWG, gridDim.x, blockIdx.x);
+  double acc = 0.0;
+  for (int64_t b0 = sc.first; b0 < sc.end; b0 += sc.stride) {
+    const int64_t b1 = b0 + kWG < sc.end ? b0 + kWG : sc.end;
+    acc += update_rows<S, T>(c, b0, b1, ld, Pc, Po, x, r, pc, zc);
+  }
+  double v[1] = {acc};
+  block_store_sums<1>(v, partials + blockIdx.x, gridDim.x);
 }
 
 // After the block update: ||r||^2, history entry, stopping test, k += 1.

@@ -32,6 +32,8 @@ struct CsrArgs {
   const int64_t *slice_off;
   const int32_t *slice_w;
   int64_t nslices;
+  int sell_xcd;      // 1: slices dealt out XCD-interleaved (matrix larger than the
+                     // memory-side cache), 0: a contiguous chunk per workgroup
 };
 
 template <typename T>
@@ -185,44 +187,107 @@ __device__ __forceinline__ void csr_rows_direct(const CsrArgs<T> &A, const T *__
 // column indices and one of the values, independent of any row pointer.
 // Padded entries (column -1) are masked out of the sum: each row's sum has
 // the same terms, order and rounding as the CSR product.
+
+// Address of stored entry u of the slice row `lane`.  Entries past the
+// slice width re-read its last entry, and a slice of width 0 reads entry 0 of
+// the arrays (which always hold at least one entry, not necessarily
+// initialised): every address is valid, so the loads need no branches.
+__device__ __forceinline__ int64_t sell_entry(int64_t off, int w, int u, int lane) {
+  const int uu = (u < w) ? u : w - 1;
+  return (w > 0) ? off + (int64_t)uu * kWave + lane : 0;
+}
+
+// Sliced-ELL product: the workgroup takes pieces of 4 consecutive slices,
+// one per wavefront: its contiguous chunk in order, or, for a matrix larger
+// than the memory-side cache, XCD-interleaved pieces (an XCD's workgroups
+// then stream neighbouring slices together, which keeps HBM pages and the
+// gathered x shared; measured 8 % faster at 256^3, 2 % slower on a
+// cache-resident 128^3 matrix).  The headers
+// (offset, width) of up to 64 of its slices are read once, one per lane, and
+// broadcast when a slice is processed.  The column indices of the next
+// slice's first U entries are loaded right after the current slice's gathers
+// and values, so they are in flight while the current slice is summed and
+// stored, and the next gathers can be issued at once.  Only entries inside
+// the width with a column >= 0 enter a sum (the others gather the row's own
+// x): each row's sum has the same terms, order and rounding as the CSR
+// product.
 template <typename T, class Pre, class F>
 __device__ __forceinline__ void sell_rows(const CsrArgs<T> &A, const T *__restrict__ x, Pre &&pre,
                                           F &&f, T xs) {
 #pragma clang fp contract(off)
   constexpr int U = 8;
-  int64_t s0, s1;
-  block_chunk(A.nslices, logical_block(), gridDim.x, s0, s1);
+  constexpr int WS = kWG / kWave;
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-  for (int64_t sl = s0 + wave; sl < s1; sl += kWG / kWave) {
-    const int64_t row = sl * kWave + lane;
-    const bool live = row < A.n;
-    const int64_t rowc = live ? row : A.n - 1;
-    const int64_t off = A.slice_off[sl];
-    const int w = A.slice_w[sl];
-    const auto p = pre(rowc);
-    T acc = 0;
-    for (int u0 = 0; u0 < w; u0 += U) {
-      int ci[U];
-      T vv[U];
-      bool ok[U];
+  // the workgroup's slices: pieces of WS slices (one per wavefront) at
+  // first, first + WSX, ... below s1
+  int64_t first, WSX, s1;
+  if (A.sell_xcd) {
+    const XcdSched sc = xcd_sched(A.nslices, WS, gridDim.x, blockIdx.x);
+    first = sc.first + wave;
+    WSX = sc.stride;
+    s1 = sc.end;
+  } else {
+    int64_t s0;
+    block_chunk(A.nslices, logical_block(), gridDim.x, s0, s1);
+    first = s0 + wave;
+    WSX = WS;
+  }
+  for (int64_t g0 = first; g0 < s1; g0 += WSX * kWave) {
+    // this wavefront's slices g0 + WSX t, t < cnt (cnt >= 1 since g0 < s1)
+    const int64_t left = (s1 - g0 + WSX - 1) / WSX;
+    const int cnt = left < kWave ? (int)left : kWave;
+    const int64_t hs = g0 + WSX * (lane < cnt ? lane : cnt - 1);
+    const int64_t hoff = A.slice_off[hs];
+    const int hw = A.slice_w[hs];
+    const int hlo = (int)(uint32_t)hoff, hhi = (int)(hoff >> 32);
+    auto header = [&](int t, int64_t &off, int &w) {
+      const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane(hlo, t);
+      const int64_t hi = __builtin_amdgcn_readlane(hhi, t);
+      off = (int64_t)((uint64_t)hi << 32 | lo);
+      w = __builtin_amdgcn_readlane(hw, t);
+    };
+    int64_t off;
+    int w;
+    header(0, off, w);
+    int cc[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int uu = (u0 + u < w) ? u0 + u : w - 1;
-        const int64_t e = off + (int64_t)uu * kWave + lane;
-        const int c = A.sell_col[e];
-        ok[u] = (u0 + u < w) && c >= 0;
-        ci[u] = c >= 0 ? c : (int)rowc;
-        vv[u] = A.sell_val[e];
+    for (int u = 0; u < U; ++u) cc[u] = A.sell_col[sell_entry(off, w, u, lane)];
+    for (int t = 0; t < cnt; ++t) {
+      const int64_t row = (g0 + WSX * t) * kWave + lane;
+      const bool live = row < A.n;
+      const int64_t rowc = live ? row : A.n - 1;
+      const auto p = pre(rowc);
+      const int64_t so = off;   // this slice's header (off, w move on to the next slice)
+      const int sw = w;
+      T acc = 0;
+      for (int u0 = 0; u0 < (sw > 0 ? sw : 1); u0 += U) {
+        if (u0 > 0) {
+#pragma unroll
+          for (int u = 0; u < U; ++u) cc[u] = A.sell_col[sell_entry(so, sw, u0 + u, lane)];
+        }
+        T xg[U], vv[U];
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          ok[u] = (u0 + u < sw) && cc[u] >= 0;
+          xg[u] = x[ok[u] ? cc[u] : (int)rowc];
+          vv[u] = A.sell_val[sell_entry(so, sw, u0 + u, lane)];
+        }
+        if (u0 + U >= sw) {
+          // last pass of this slice: start on the next slice's columns
+          header(t + 1 < cnt ? t + 1 : t, off, w);
+#pragma unroll
+          for (int u = 0; u < U; ++u) cc[u] = A.sell_col[sell_entry(off, w, u, lane)];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const T pu = vv[u] * (xs * xg[u]);
+          const T sum = acc + pu;
+          acc = ok[u] ? sum : acc;
+        }
       }
-#pragma unroll
-      for (int u = 0; u < U; ++u) vv[u] = vv[u] * (xs * x[ci[u]]);
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const T t = acc + vv[u];
-        acc = ok[u] ? t : acc;
-      }
+      if (live) f(row, acc, p);
     }
-    if (live) f(row, acc, p);
   }
 }
 
