@@ -78,6 +78,8 @@ def lib():
             _lib.orc_pcg.restype = C.c_int
             _lib.orc_pcg.argtypes = [C.POINTER(_Op), C.c_int, C.c_void_p, C.c_void_p, C.c_double,
                                      C.c_int, C.POINTER(_Res)]
+            _lib.orc_pfcg.restype = C.c_int
+            _lib.orc_pfcg.argtypes = _lib.orc_pcg.argtypes
             _lib.orc_sstep.restype = C.c_int
             _lib.orc_sstep.argtypes = [C.POINTER(_Op), C.c_int, C.c_void_p, C.c_void_p, C.c_int,
                                        C.c_double, C.c_int, C.c_int, C.POINTER(_Res),
@@ -233,6 +235,17 @@ def pcg(op: Operator, b, x0=None, rtol=1e-8, maxit=10000, prec=PREC_JACOBI):
     hist = np.zeros(maxit + 2)
     res = _Res(hist=_ptr(hist), hist_cap=hist.size)
     lib().orc_pcg(C.byref(op._op), prec, _ptr(b), _ptr(x), rtol, maxit, C.byref(res))
+    return _result(res, hist, x)
+
+
+def pfcg(op: Operator, b, x0=None, rtol=1e-8, maxit=10000, prec=PREC_JACOBI):
+    """Alg. 2 (PFCG) on the oracle operator; returns a Result with x and history.
+    maxit counts every step, the one before the loop included."""
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+    hist = np.zeros(maxit + 2)
+    res = _Res(hist=_ptr(hist), hist_cap=hist.size)
+    lib().orc_pfcg(C.byref(op._op), prec, _ptr(b), _ptr(x), rtol, maxit, C.byref(res))
     return _result(res, hist, x)
 
 

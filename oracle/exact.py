@@ -1,10 +1,12 @@
-"""Exact rational versions of Alg. 1 (PCG-HS) and Alg. 3-6 (s-step PCG).
+"""Exact rational versions of Alg. 1 (PCG-HS), Alg. 2 (PFCG) and Alg. 3-6
+(s-step PCG).
 
 TEST INFRASTRUCTURE ONLY.  Pure Python with ``fractions.Fraction`` for tiny
 dense problems (n up to a few dozen): every operation is exact, so the s-step
 iterate x_i must EQUAL the standard PCG iterate x_{i*s} (both minimise the
 A-norm of the error over the same preconditioned Krylov space; Sec. II-A), and
-both reach the exact solution after n standard steps.
+both reach the exact solution after n standard steps.  With a fixed
+preconditioner, PFCG's iterates equal PCG's step for step.
 
 The matrix A and the diagonal preconditioner B are given as integer/Fraction
 lists.  Index names follow the paper (1-based in comments).
@@ -49,6 +51,44 @@ def pcg(A, b, bdiag, iters):
         ur = ur_new
         xs.append(list(x))
     return xs
+
+
+def pfcg(A, b, bdiag, iters):
+    """Alg. 2 for exactly ``iters`` steps in all (the one before the loop
+    included; fewer if r = 0).  Returns ([x_0, x_1, ...], [p_0, p_1, ...])."""
+    n = len(b)
+    x = [Fr(0)] * n
+    r = list(map(Fr, b))                       # r0 = b - A x0, x0 = 0
+    xs, ps = [list(x)], []
+    if iters < 1 or all(v == 0 for v in r):
+        return xs, ps
+    u = _binv(bdiag, r)                        # u0 = p0 = B^{-1} r0
+    p = list(u)
+    w = _mv(A, u)                              # w0 = s0 = A u0
+    s = list(w)
+    alpha = _dot(u, r)                         # alpha0 = u0^T r0
+    rho = _dot(p, s)                           # beta0 = rho0 = p0^T s0
+    x = [xi + alpha / rho * pi for xi, pi in zip(x, p)]
+    r = [ri - alpha / rho * si for ri, si in zip(r, s)]
+    xs.append(list(x))
+    ps.append(list(p))
+    for _ in range(1, iters):
+        if all(v == 0 for v in r):
+            break
+        u = _binv(bdiag, r)                    # u_k = B^{-1} r_k
+        w = _mv(A, u)                          # w_k = A u_k
+        alpha = _dot(u, r)
+        beta = _dot(u, w)
+        gamma = _dot(u, s)                     # u_k^T s_{k-1}
+        rho_k = beta - gamma * gamma / rho
+        p = [ui - gamma / rho * pi for ui, pi in zip(u, p)]
+        x = [xi + alpha / rho_k * pi for xi, pi in zip(x, p)]
+        s = [wi - gamma / rho * si for wi, si in zip(w, s)]
+        r = [ri - alpha / rho_k * si for ri, si in zip(r, s)]
+        rho = rho_k
+        xs.append(list(x))
+        ps.append(list(p))
+    return xs, ps
 
 
 def _solve(M, rhs):

@@ -16,6 +16,7 @@
  * reduced Conjugate Gradient Variants for GPU-accelerated Clusters",
  * Euromicro PDP 2025 (arXiv 2501.03743).
  *   Alg. 1  PCG-HS                      -> orc_pcg
+ *   Alg. 2  PFCG (one reduction a step) -> orc_pfcg
  *   Alg. 3  PCGs (outer loop)           -> orc_sstep
  *   Alg. 4  pMPK (matrix powers)        -> mpk()
  *   Alg. 5  cvm (2s moments)            -> cvm()
@@ -37,7 +38,11 @@
  *     of the lower triangle; the factor of W_{i-1} is reused for beta;
  *     a pivot (before the square root) <= s * 2^-52 * |W_jj| or a non-finite
  *     value is a breakdown, and so is |alpha_{i-1}(s)| <= 1e-300;
- *   - with P1 = 0 at k = 0 (Alg. 3) the P_{i-1} beta terms are skipped.
+ *   - with P1 = 0 at k = 0 (Alg. 3) the P_{i-1} beta terms are skipped;
+ *   - Alg. 2 returns the newest iterate x_{k+1} (the one whose residual passed
+ *     the test), counts every step including the one before its loop against
+ *     maxit, and reports a breakdown when rho_k is not positive or a step
+ *     length is not finite.
  */
 #include <math.h>
 #include <stdint.h>
@@ -409,6 +414,100 @@ int orc_pcg(const orc_op *A, int prec, const double *b, double *x, double rtol,
   res->cg_equiv = it;
   res->status = status;
   free(r); free(u); free(p); free(sv); free(dinv);
+  return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Alg. 2: flexible PCG with one global reduction per step (PFCG)            */
+/* ------------------------------------------------------------------------ */
+
+int orc_pfcg(const orc_op *A, int prec, const double *b, double *x, double rtol,
+             int maxit, orc_result *res) {
+  res->status = ORC_EINVAL;
+  res->outer = res->cg_equiv = 0;
+  res->hist_len = 0;
+  res->true_rel = NAN;
+  if (!op_check(A) || maxit < 0) return ORC_EINVAL;
+  int64_t n = A->n;
+  double *r = malloc((size_t)n * sizeof(double));
+  double *u = malloc((size_t)n * sizeof(double));
+  double *p = malloc((size_t)n * sizeof(double));
+  double *w = malloc((size_t)n * sizeof(double));
+  double *sv = malloc((size_t)n * sizeof(double));
+  double *dinv = malloc((size_t)n * sizeof(double));
+  if (!r || !u || !p || !w || !sv || !dinv) {
+    free(r); free(u); free(p); free(w); free(sv); free(dinv);
+    res->status = ORC_ENOMEM;
+    return ORC_ENOMEM;
+  }
+  op_diag(A, dinv);
+  for (int64_t i = 0; i < n; ++i) dinv[i] = 1.0 / dinv[i];
+
+  double bn = nrm2(n, b);
+  if (bn == 0.0) {
+    memset(x, 0, (size_t)n * sizeof(double));
+    hist_push(res, 0.0);
+    res->status = ORC_OK;
+    res->true_rel = 0.0;
+    free(r); free(u); free(p); free(w); free(sv); free(dinv);
+    return ORC_OK;
+  }
+  int status = ORC_NOT_CONVERGED;
+  residual(A, b, x, r, w);                  /* r_0 = b - A x_0 */
+  double rn = nrm2(n, r);
+  hist_push(res, rn / bn);
+  int it = 0;
+  if (rn <= rtol * bn) {
+    status = ORC_OK;
+  } else if (maxit > 0) {
+    /* the step before the loop */
+    prec_apply(prec, n, dinv, r, u);        /* u_0 = p_0 = B^{-1} r_0 */
+    memcpy(p, u, (size_t)n * sizeof(double));
+    orc_apply(A, u, w);                     /* w_0 = s_0 = A u_0 */
+    memcpy(sv, w, (size_t)n * sizeof(double));
+    double alpha = orc_dot(n, u, r);        /* alpha_0 = u_0^T r_0 */
+    double rho = orc_dot(n, p, sv);         /* beta_0 = rho_0 = p_0^T s_0 */
+    double step = alpha / rho;
+    if (!(rho > 0.0) || !isfinite(step)) {
+      status = ORC_BREAKDOWN;
+    } else {
+      for (int64_t i = 0; i < n; ++i) x[i] += step * p[i];    /* x_1 */
+      for (int64_t i = 0; i < n; ++i) r[i] -= step * sv[i];   /* r_1 */
+      it = 1;
+      rn = nrm2(n, r);
+      hist_push(res, rn / bn);
+      if (rn <= rtol * bn) status = ORC_OK;
+      for (int k = 1; k < maxit && status == ORC_NOT_CONVERGED; ++k) {
+        prec_apply(prec, n, dinv, r, u);    /* u_k = B^{-1} r_k */
+        orc_apply(A, u, w);                 /* w_k = A u_k */
+        alpha = orc_dot(n, u, r);           /* alpha_k = u_k^T r_k */
+        double beta = orc_dot(n, u, w);     /* beta_k = u_k^T w_k */
+        double gamma = orc_dot(n, u, sv);   /* gamma_k = u_k^T s_{k-1} */
+        double rho_k = beta - gamma * gamma / rho;
+        double g = gamma / rho;             /* gamma_k / rho_{k-1} */
+        step = alpha / rho_k;               /* alpha_k / rho_k */
+        if (!(rho_k > 0.0) || !isfinite(step) || !isfinite(g)) {
+          status = ORC_BREAKDOWN;
+          break;
+        }
+        for (int64_t i = 0; i < n; ++i) p[i] = u[i] - g * p[i];     /* p_k */
+        for (int64_t i = 0; i < n; ++i) x[i] += step * p[i];        /* x_{k+1} */
+        for (int64_t i = 0; i < n; ++i) sv[i] = w[i] - g * sv[i];   /* s_k */
+        for (int64_t i = 0; i < n; ++i) r[i] -= step * sv[i];       /* r_{k+1} */
+        rho = rho_k;
+        it = k + 1;
+        rn = nrm2(n, r);
+        hist_push(res, rn / bn);
+        if (rn <= rtol * bn) status = ORC_OK;
+      }
+    }
+  }
+  residual(A, b, x, r, w);
+  res->true_rel = nrm2(n, r) / bn;
+  res->outer = it;
+  res->cg_equiv = it;
+  res->status = status;
+  free(r); free(u); free(p); free(w); free(sv); free(dinv);
   return status;
 }
 

@@ -1,0 +1,156 @@
+"""Pins of the oracle's Alg. 2 (PFCG, one global reduction per step).
+
+PFCG is the flexible variant of preconditioned CG; with a fixed SPD
+preconditioner it generates the same iterates as Alg. 1 in exact arithmetic
+(its rho_k is the p_k^T A p_k of the standard recurrence, obtained from the
+three coupled dot products instead of a second reduction).  The pins:
+exact rational PFCG equals exact rational PCG step for step and reaches the
+solution in n steps; its directions are A-conjugate; the FP64 oracle follows
+the exact iterates to rounding; it stops after as many steps as the
+preconditioned operator has distinct eigenvalues; it solves manufactured and
+dense-solved systems; a zero pivot rho is reported as a breakdown; and the
+paper's count of 514 steps at 250^3 (Sec. V-B states it for PFCG and for
+PCGs with s = 1).
+"""
+from fractions import Fraction as Fr
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import exact
+from paper_2501_03743_amd import workloads as wl
+
+
+def _spd_int(n, seed):
+    """Random SPD integer matrix M^T M + n I and a positive integer diagonal."""
+    g = np.random.default_rng(seed)
+    M = g.integers(-3, 4, size=(n, n))
+    A = M.T @ M + n * np.eye(n, dtype=np.int64)
+    bdiag = [int(v) for v in np.diag(A)]
+    b = [int(v) for v in g.integers(-5, 6, size=n)]
+    return A, bdiag, b
+
+
+def _dense_op(A):
+    n = A.shape[0]
+    rowptr = np.arange(0, n * n + 1, n, dtype=np.int32)
+    colind = np.tile(np.arange(n, dtype=np.int32), n)
+    val = np.ascontiguousarray(A, dtype=np.float64).reshape(-1)
+    return oracle.Operator("csr", csr=(rowptr, colind, val))
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+@pytest.mark.parametrize("jacobi", [False, True])
+def test_exact_pfcg_equals_exact_pcg(seed, jacobi):
+    n = 7
+    A, bdiag, b = _spd_int(n, seed)
+    Al = [[Fr(int(v)) for v in row] for row in A]
+    bd = [Fr(d) for d in bdiag] if jacobi else [Fr(1)] * n
+    xs_pcg = exact.pcg(Al, b, bd, n)
+    xs_pf, ps = exact.pfcg(Al, b, bd, n)
+    assert len(xs_pf) == len(xs_pcg)
+    for k, (a, c) in enumerate(zip(xs_pf, xs_pcg)):
+        assert a == c, k
+    # the exact solution after n steps
+    assert exact._mv(Al, xs_pf[-1]) == [Fr(v) for v in b]
+    # A-conjugate directions
+    for i in range(len(ps)):
+        Api = exact._mv(Al, ps[i])
+        for j in range(i):
+            assert exact._dot(ps[j], Api) == 0, (i, j)
+
+
+@pytest.mark.parametrize("jacobi", [False, True])
+def test_oracle_follows_exact_iterates(jacobi):
+    n = 9
+    A, bdiag, b = _spd_int(n, 5)
+    Al = [[Fr(int(v)) for v in row] for row in A]
+    bd = [Fr(d) for d in bdiag] if jacobi else [Fr(1)] * n
+    xs, _ = exact.pfcg(Al, b, bd, n)
+    op = _dense_op(A)
+    prec = oracle.PREC_JACOBI if jacobi else oracle.PREC_NONE
+    bf = np.array(b, dtype=np.float64)
+    for k in range(1, n + 1):
+        r = oracle.pfcg(op, bf, rtol=0.0, maxit=k, prec=prec)
+        assert r.outer == k
+        ref = np.array([float(v) for v in xs[k]])
+        err = np.linalg.norm(r.x - ref) / np.linalg.norm(ref)
+        assert err <= 1e-12, (k, err)
+
+
+def test_stops_after_distinct_eigenvalue_count():
+    # A = Q diag(lambda) Q^T with 4 distinct eigenvalues: Krylov methods of
+    # the CG family reach the solution in 4 steps
+    n = 40
+    g = np.random.default_rng(3)
+    Q, _ = np.linalg.qr(g.standard_normal((n, n)))
+    lam = np.repeat([1.0, 2.5, 4.0, 9.0], n // 4)
+    A = (Q * lam) @ Q.T
+    A = 0.5 * (A + A.T)
+    b = g.standard_normal(n)
+    r = oracle.pfcg(_dense_op(A), b, rtol=1e-10, maxit=50, prec=oracle.PREC_NONE)
+    assert r.status == oracle.OK and r.outer == 4, (r.status, r.outer)
+
+
+@pytest.mark.parametrize("kind,shape", [("3d7_vark", (9, 8, 7)), ("3d27", (7, 6, 8)), ("2d5", (20, 17, 1))])
+def test_manufactured_and_dense_solutions(kind, shape):
+    k = np.exp(wl.gaussian_random_field(shape, 1.0, 0.2, 4)) if kind == "3d7_vark" else None
+    op = oracle.Operator(kind, shape, k=k)
+    n = op.n
+    xstar = wl.uniform_solution(n, 2)
+    b = op.apply(xstar)
+    r = oracle.pfcg(op, b, rtol=1e-12)
+    assert r.status == oracle.OK and r.true_rel <= 2e-12
+    # dense solve of the same operator
+    D = np.stack([op.apply(e) for e in np.eye(n)], axis=1)
+    xd = np.linalg.solve(D, b)
+    cond = np.linalg.cond(D)
+    assert np.linalg.norm(r.x - xd) / np.linalg.norm(xd) <= 10 * cond * 1e-12
+    assert np.linalg.norm(xd - xstar) / np.linalg.norm(xstar) <= 1e-10
+    # the history starts at ||b||/||b|| (x0 = 0) and ends below the tolerance
+    assert r.hist[0] == pytest.approx(1.0) and r.hist[r.outer] <= 1e-12
+
+
+def test_pfcg_matches_pcg_in_floating_point():
+    shape = (14, 12, 10)
+    k = np.exp(wl.gaussian_random_field(shape, 0.5, 0.1, 1))
+    op = oracle.Operator("3d7_vark", shape, k=k)
+    b = wl.normal_rhs(op.n, 6)
+    a = oracle.pcg(op, b, rtol=1e-10)
+    c = oracle.pfcg(op, b, rtol=1e-10)
+    assert a.status == c.status == oracle.OK
+    assert abs(a.outer - c.outer) <= 1
+    assert np.linalg.norm(a.x - c.x) / np.linalg.norm(a.x) <= 1e-9
+    m = min(a.outer, c.outer)
+    np.testing.assert_allclose(c.hist[:m], a.hist[:m], rtol=1e-6)
+
+
+def test_breakdown_zero_rhs_and_initial_guess():
+    # indefinite: rho_0 = u_0^T A u_0 = 0 for b = (1, 1), A = diag(1, -1)
+    A = np.diag([1.0, -1.0])
+    r = oracle.pfcg(_dense_op(A), np.ones(2), rtol=1e-8, prec=oracle.PREC_NONE)
+    assert r.status == oracle.BREAKDOWN and r.outer == 0
+    op = oracle.Operator("3d7", (6, 5, 4))
+    z = oracle.pfcg(op, np.zeros(op.n))
+    assert z.status == oracle.OK and not z.x.any() and z.outer == 0
+    # an exact initial guess needs no step
+    xstar = wl.uniform_solution(op.n, 1)
+    b = op.apply(xstar)
+    e = oracle.pfcg(op, b, x0=xstar, rtol=1e-8)
+    assert e.status == oracle.OK and e.outer == 0 and np.array_equal(e.x, xstar)
+    # maxit = 0 leaves x0 alone
+    m = oracle.pfcg(op, b, rtol=1e-8, maxit=0)
+    assert m.status == oracle.NOT_CONVERGED and m.outer == 0 and not m.x.any()
+
+
+@pytest.mark.slow
+def test_paper_iteration_count_250cubed_pfcg():
+    """Sec. V-B: 3D Poisson 250^3, b = 1, no preconditioner, relative residual
+    1e-6: PFCG needs 514 iterations on one GPU (a few percent allowed, as the
+    stopping details are not fully stated)."""
+    N = 250
+    op = oracle.Operator("3d7", (N, N, N))
+    r = oracle.pfcg(op, np.ones(N ** 3), rtol=1e-6, maxit=2000, prec=oracle.PREC_NONE)
+    assert r.status == oracle.OK
+    assert abs(r.outer - 514) <= 0.03 * 514, r.outer
