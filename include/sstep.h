@@ -72,6 +72,8 @@ typedef struct ssp_matrix ssp_matrix;
 /* ---- solver options ------------------------------------------------------ */
 #define SSP_METHOD_SSTEP 0    /* Alg. 3 with Alg. 4-6                           */
 #define SSP_METHOD_PCG 1      /* Alg. 1                                         */
+#define SSP_METHOD_PFCG 2     /* Alg. 2: flexible PCG with one reduction per
+                                 step (the paper's comparator); s is ignored    */
 
 #define SSP_PRECISION_FP64 0
 #define SSP_PRECISION_MIXED_IR 1  /* FP32 inner s-step (matrix powers and block
@@ -184,9 +186,12 @@ int ssp_mpk(ssp_handle *h, const ssp_matrix *A, const double *r, int s, double *
 
 /* Solves A x = b.  b (n) and x (n, in: x0, out: solution) are DEVICE pointers
  * owned by the caller.  s in 1..SSP_SMAX (and s <= n) is the block size of
- * the s-step method (ignored by SSP_METHOD_PCG).  Stops when the recursive
- * residual satisfies ||r||_2 <= rtol ||b||_2, tested once per outer
- * iteration; maxit counts CG-equivalent steps (outer limit ceil(maxit/s)).
+ * the s-step method (ignored by SSP_METHOD_PCG and SSP_METHOD_PFCG).  Stops
+ * when the recursive residual satisfies ||r||_2 <= rtol ||b||_2, tested once
+ * per outer iteration; maxit counts CG-equivalent steps (outer limit
+ * ceil(maxit/s); for PFCG every step counts, the one before the loop of
+ * Alg. 2 included).  Mixed precision is implemented for the s-step method
+ * only (SSP_EUNSUPPORTED otherwise).
  * opts may be NULL (defaults: s-step, FP64).  b = 0 gives x = 0 and SSP_OK.
  * Returns SSP_OK, SSP_NOT_CONVERGED, SSP_BREAKDOWN or an error.  Blocks until
  * the result is in x. */

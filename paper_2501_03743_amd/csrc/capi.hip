@@ -535,6 +535,53 @@ int solve_pcg(ssp_handle *h, const ssp_matrix *A, const double *b, double *x, do
   return finish_solve(h, A, b, x, 1);
 }
 
+// Alg. 2 (PFCG): per step one operator pass with the three coupled dot
+// products (one reduction) and one fused update with ||r||^2.  p and s live
+// in the first block's two columns, w and the stored B^-1 r (Jacobi vector
+// only) in the second block's.
+int solve_pfcg(ssp_handle *h, const ssp_matrix *A, const double *b, double *x, double rtol,
+               int maxit, const ssp_opts *o) {
+  const int fixed = (o && o->fixed_outer > 0) ? o->fixed_outer : 0;
+  const int outer_max = fixed ? fixed : maxit;
+  int rc = ensure_workspace(h, A->n, 1, outer_max + 1, false);
+  if (rc) return rc;
+  Workspace &w = h->ws;
+  rc = state_init(h, 1, outer_max, fixed ? 1 : 0, rtol, w.hist_cap);
+  if (rc) return rc;
+  double *tag = nullptr;
+  const Prec<double> pc = prec_of(A, tag);
+  double *p = w.P1, *sv = w.P1 + w.ld, *wv = w.P2;
+  double *u = pc.dinv ? w.P2 + w.ld : nullptr;
+  HIPCHK(h, hipMemsetAsync(p, 0, sizeof(double) * A->n, h->stream));
+  HIPCHK(h, hipMemsetAsync(sv, 0, sizeof(double) * A->n, h->stream));
+  rc = launch_op<double>(h, A, x, EpiPfcgInit{b, w.r, u, pc, w.hist}, 3);
+  if (rc) return rc;
+  const int every = (o && o->check_every > 0) ? o->check_every : 32;
+  const int G = grid_rows(A->n);
+  int k = 0;
+  rc = read_state(h, false);
+  if (rc) return rc;
+  while (k < outer_max && h->h_read->status == ST_RUNNING) {
+    const int m = std::min(every, outer_max - k);
+    for (int i = 0; i < m; ++i, ++k) {
+      h->prof_iter = k;
+      rc = launch_op<double>(h, A, u ? u : w.r, EpiPfcgSpmv{w.r, u, sv, wv, pc.dc}, 0,
+                             u ? 1.0 : pc.dc);
+      if (rc) return rc;
+      prof_begin(h, 2);
+      k_pfcg_update<<<G, kWG, 0, h->stream>>>(A->n, x, w.r, p, sv, wv, u, pc, h->st,
+                                              w.partials);
+      k_finalize<FinUpdate><<<1, kWG, 0, h->stream>>>(FinUpdate{w.hist}, h->st, w.partials, G);
+      prof_end(h);
+      LAUNCHCHK(h);
+    }
+    h->prof_iter = -1;
+    rc = read_state(h, false);
+    if (rc) return rc;
+  }
+  return finish_solve(h, A, b, x, 1);
+}
+
 // Mixed precision: FP32 inner s-step solves (matrix powers and block updates
 // in FP32; moments, s x s solves and the inner stopping test in FP64) of
 // A d = r inside FP64 iterative refinement x += d, r = b - A x.
@@ -957,7 +1004,7 @@ int ssp_solve(ssp_handle *h, const ssp_matrix *A, const double *b, double *x, in
   if (!(rtol >= 0.0) || maxit < 0) return fail(h, SSP_EINVAL, "ssp_solve: rtol must be >= 0 and maxit >= 0");
   if (method == SSP_METHOD_SSTEP && (s < 1 || s > SSP_SMAX || s > A->n))
     return fail(h, SSP_EINVAL, "ssp_solve: s out of range (s=" + std::to_string(s) + ")");
-  if (method != SSP_METHOD_SSTEP && method != SSP_METHOD_PCG)
+  if (method != SSP_METHOD_SSTEP && method != SSP_METHOD_PCG && method != SSP_METHOD_PFCG)
     return fail(h, SSP_EINVAL, "ssp_solve: unknown method " + std::to_string(method));
   if (precision != SSP_PRECISION_FP64 && precision != SSP_PRECISION_MIXED_IR)
     return fail(h, SSP_EINVAL, "ssp_solve: unknown precision " + std::to_string(precision));
@@ -981,6 +1028,7 @@ int ssp_solve(ssp_handle *h, const ssp_matrix *A, const double *b, double *x, in
   if (precision == SSP_PRECISION_MIXED_IR)
     return solve_mixed(h, const_cast<ssp_matrix *>(A), b, x, s, rtol, maxit, opts);
   if (method == SSP_METHOD_PCG) return solve_pcg(h, A, b, x, rtol, maxit, opts);
+  if (method == SSP_METHOD_PFCG) return solve_pfcg(h, A, b, x, rtol, maxit, opts);
   return solve_sstep(h, A, b, x, s, rtol, maxit, opts);
 }
 

@@ -217,6 +217,74 @@ struct EpiPcgSpmv {
   }
 };
 
+// PFCG start (Alg. 2): r = b - A x0 (and u = B^-1 r when the Jacobi scaling
+// is a stored vector), ||b||^2 and ||r||^2.  rho_{-1} = 1: with p and s
+// zero, the general step then gives exactly the paper's first step
+// (gamma = 0, p_0 = u_0, s_0 = w_0, rho_0 = beta_0).
+struct EpiPfcgInit {
+  static constexpr int NP = 2;
+  static constexpr bool kCheck = false;
+  const double *b;
+  double *r, *u;     // u: nullptr for a constant scaling (never stored)
+  Prec<double> pc;
+  double *hist;
+  __device__ __forceinline__ void row(int64_t i, double v, double *part) const {
+#pragma clang fp contract(off)
+    const double bi = b[i];
+    const double ri = bi - v;
+    r[i] = ri;
+    if (u) u[i] = pc.apply(i, ri);
+    part[0] += bi * bi;
+    part[1] += ri * ri;
+  }
+  __device__ __forceinline__ void finish(DevState *st, const double *tot) const {
+    if (threadIdx.x == 0) {
+      st->rho = 1.0;
+      start_status(st, tot[0], tot[1], hist);
+    }
+  }
+};
+
+// PFCG step, first half (Alg. 2): w = A u with u = B^-1 r, and the three
+// coupled dot products alpha = u^T r, beta = u^T w, gamma = u^T s_{k-1} in
+// the same pass (one reduction).  For a constant scaling c the operator is
+// applied to c r (the visitor's scale) and u_i = c r_i is formed here with
+// the same rounding.  The finalisation forms rho_k = beta - gamma^2/rho_{k-1}
+// and the two coefficients of the update.
+struct EpiPfcgSpmv {
+  static constexpr int NP = 3;
+  static constexpr bool kCheck = true;
+  const double *r, *u, *sv;   // u: stored B^-1 r, or nullptr (constant c)
+  double *w;
+  double c;
+  __device__ __forceinline__ void row(int64_t i, double v, double *part) const {
+#pragma clang fp contract(off)
+    w[i] = v;
+    const double ri = r[i];
+    const double ui = u ? u[i] : c * ri;
+    part[0] += ui * ri;
+    part[1] += ui * v;
+    part[2] += ui * sv[i];
+  }
+  __device__ __forceinline__ void finish(DevState *st, const double *tot) const {
+#pragma clang fp contract(off)
+    if (threadIdx.x == 0) {
+      const double alpha = tot[0], beta = tot[1], gamma = tot[2];
+      const double rho_prev = st->rho;
+      const double rho = beta - gamma * gamma / rho_prev;
+      const double g = gamma / rho_prev;       // gamma_k / rho_{k-1}
+      const double step = alpha / rho;         // alpha_k / rho_k
+      if (!(rho > 0.0) || !isfinite(step) || !isfinite(g)) {
+        st->status = ST_BREAKDOWN;
+      } else {
+        st->rho = rho;
+        st->pcg_alpha = step;
+        st->pcg_beta = g;
+      }
+    }
+  }
+};
+
 // ||b - A x||^2 of the final iterate (runs whatever the status).
 struct EpiTrueRes {
   static constexpr int NP = 1;
@@ -648,6 +716,44 @@ struct FinPcgUpdate {
     }
   }
 };
+
+// PFCG step, second half (Alg. 2): p = u - g p, x += a p, s = w - g s,
+// r -= a s (u = B^-1 r of the old r; stored u is refreshed from the new r),
+// with ||r||^2 partials finished by FinUpdate.  Rows in XCD-interleaved
+// pieces; the partial is stored at the hardware block index.
+static __global__ __attribute__((unused)) __launch_bounds__(kWG) void k_pfcg_update(
+    int64_t n, double *__restrict__ x, double *__restrict__ r, double *__restrict__ p,
+    double *__restrict__ sv, const double *__restrict__ w, double *__restrict__ u,
+    Prec<double> pc, DevState *st, double *partials) {
+#pragma clang fp contract(off)
+  if (st->status != ST_RUNNING) return;
+  const double a = st->pcg_alpha, g = st->pcg_beta;
+  const XcdSched sc = xcd_sched(n, kWG, gridDim.x, blockIdx.x);
+  double rr = 0.0;
+  for (int64_t b0 = sc.first; b0 < sc.end; b0 += sc.stride) {
+    const int64_t b1 = b0 + kWG < sc.end ? b0 + kWG : sc.end;
+    for (int64_t i = b0 + threadIdx.x; i < b1; i += kWG) {
+      const double ri = r[i];
+      const double ui = u ? u[i] : pc.dc * ri;
+      const double gp = g * p[i];
+      const double pn = ui - gp;
+      const double ap = a * pn;
+      const double xn = x[i] + ap;
+      const double gs = g * sv[i];
+      const double sn = w[i] - gs;
+      const double as = a * sn;
+      const double rn = ri - as;
+      p[i] = pn;
+      x[i] = xn;
+      sv[i] = sn;
+      r[i] = rn;
+      if (u) u[i] = pc.apply(i, rn);
+      rr += rn * rn;
+    }
+  }
+  double v[1] = {rr};
+  block_store_sums<1>(v, partials + blockIdx.x, gridDim.x);
+}
 
 // PCG direction: p = u + beta p with u = B^-1 r recomputed from r.
 static __global__ __attribute__((unused)) __launch_bounds__(kWG) void k_pcg_direction(int64_t n, const double *__restrict__ r,

@@ -25,7 +25,7 @@ SMAX = 16
 STENCIL = {"2d5": 1, "3d7": 2, "3d27": 3, "3d7_vark": 4}
 BORROW, COPY, VALIDATE = 0, 1, 2
 PREC = {"none": 0, "jacobi": 1}
-METHOD = {"sstep": 0, "pcg": 1}
+METHOD = {"sstep": 0, "pcg": 1, "pfcg": 2}
 PRECISION = {"fp64": 0, "mixed_ir": 1}
 
 # C symbols declared in include/sstep.h (checked by the CPU tests)

@@ -50,3 +50,14 @@ def test_status_strings_and_host_side_errors(lib):
 def test_gfx950_code_object_present(lib):
     data = open(sstep.LIB_PATH, "rb").read()
     assert b"gfx950" in data
+
+
+def test_binding_constants_match_header():
+    text = open(os.path.join(ROOT, "include", "sstep.h")).read()
+    defs = dict((m.group(1), int(m.group(2)))
+                for m in re.finditer(r"#define\s+(SSP_[A-Z0-9_]+)\s+(-?\d+)\b", text))
+    for name, v in sstep.METHOD.items():
+        assert defs["SSP_METHOD_" + name.upper()] == v, name
+    for name, v in sstep.PRECISION.items():
+        assert defs["SSP_PRECISION_" + name.upper()] == v, name
+    assert sum(1 for k in defs if k.startswith("SSP_METHOD_")) == len(sstep.METHOD)

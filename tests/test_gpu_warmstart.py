@@ -33,7 +33,7 @@ def problem(H):
     A.close()
 
 
-@pytest.mark.parametrize("method", ["sstep", "pcg"])
+@pytest.mark.parametrize("method", ["sstep", "pcg", "pfcg"])
 def test_bad_guess_falls_back_to_zero_bitwise(H, problem, method):
     A, b, xsol, ref, _ = problem
     x_ref = torch.zeros_like(b)
