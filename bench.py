@@ -270,6 +270,9 @@ def main():
     ap.add_argument("--ws-eval", type=int, default=200)
     ap.add_argument("--ws-side", type=int, default=96)
     ap.add_argument("--ws-epochs", type=int, default=40)
+    ap.add_argument("--csr256-outer", type=int, default=0,
+                    help="only the 256^3 7-point CSR solve for this many outer iterations "
+                         "(s = 4, no stopping test): a short target for counter runs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only a plain 1 GiB device-to-device copy, three times (the "
                          "reference for the FETCH_SIZE / WRITE_SIZE counter scale)")
@@ -293,6 +296,15 @@ def main():
         print(json.dumps({"copy_bytes": src.numel() * 8, "copies": 3}))
         return
     H = sstep.Handle(0)
+    if args.csr256_outer > 0:
+        N3 = 256
+        A3 = H.matrix_csr_from_stencil("3d7", (N3, N3, N3))
+        b3 = torch.from_numpy(wl.normal_rhs(N3 ** 3, SEED)).cuda()
+        x3 = torch.zeros_like(b3)
+        r3 = H.solve(A3, b3, x3, s=S, fixed_outer=args.csr256_outer, profile=True)
+        print(json.dumps({"workload": "3D 7-point 256^3 CSR", "csr_form": A3.csr_form,
+                          "nnz": A3.nnz, "outer": r3.outer, "profile": r3.profile}))
+        return
     if args.warmstart:
         def log(m):
             print("[warmstart] " + m, file=sys.stderr, flush=True)
@@ -352,12 +364,14 @@ def main():
         return (time.perf_counter() - t) / reps, rr
 
     cg_t, cg_r = timed(lambda: solve(method="pcg"))
+    pf_t, pf_r = timed(lambda: solve(method="pfcg"))
     As = H.matrix_stencil("3d7", (N, N, N))
     def solve_st(**kw):
         x.zero_()
         return H.solve(As, b, x, rtol=RTOL, maxit=MAXIT, **kw)
     st_t, st_r = timed(lambda: solve_st(s=S))
     stcg_t, stcg_r = timed(lambda: solve_st(method="pcg"))
+    stpf_t, stpf_r = timed(lambda: solve_st(method="pfcg"))
     # plain SpMV per operator form / CSR kernel variant (HIP events on the same stream)
     def spmv_ms(M, reps=20):
         y = torch.empty_like(b)
@@ -421,7 +435,7 @@ def main():
     del b3, x3
 
     # 2D 5-point 64^2 (everything cache-resident, launch-bound): x* ~ U(-1,1)
-    # from seeds 0..4, b = A x*, s = 4 and standard PCG
+    # from seeds 0..4, b = A x*, s = 4, standard PCG and PFCG
     small = []
     A0 = H.matrix_csr(*[torch.from_numpy(a).cuda() for a in wl.stencil_csr("2d5", (64, 64))],
                       flags=sstep.COPY)
@@ -429,7 +443,8 @@ def main():
     for seed in range(5):
         b0 = torch.from_numpy(wl.csr_matvec(csr0, wl.uniform_solution(64 * 64, seed))).cuda()
         row = {"seed": seed}
-        for name, kw in (("sstep", {"s": S}), ("pcg", {"method": "pcg"})):
+        for name, kw in (("sstep", {"s": S}), ("pcg", {"method": "pcg"}),
+                         ("pfcg", {"method": "pfcg"})):
             x0 = torch.zeros_like(b0)
             H.solve(A0, b0, x0, rtol=RTOL, **kw)
             x0.zero_()
@@ -531,6 +546,8 @@ def main():
             "pcg_csr_tts_s": cg_t, "pcg_csr_iterations": cg_r.outer,
             "sstep_stencil_tts_s": st_t, "sstep_stencil_outer": st_r.outer,
             "pcg_stencil_tts_s": stcg_t, "pcg_stencil_iterations": stcg_r.outer,
+            "pfcg_csr_tts_s": pf_t, "pfcg_csr_iterations": pf_r.outer,
+            "pfcg_stencil_tts_s": stpf_t, "pfcg_stencil_iterations": stpf_r.outer,
             "sstep_csr_by_s": per_s,
             "spmv": spmv,
             "copy_gbs": copy_gbs,
