@@ -228,7 +228,31 @@ def _result(res, hist, x, trace=None):
     return out
 
 
-def pcg(op: Operator, b, x0=None, rtol=1e-8, maxit=10000, prec=PREC_JACOBI):
+def _restarted(run, x0, rtol, maxit, s, restarts):
+    """Residual replacement by restart: while the recursive stopping test held
+    but the true residual ||b - A x|| exceeds rtol ||b||, run the method again
+    from the current x (its first residual is the true one), at most
+    `restarts` times and within the budget of maxit CG-equivalent steps.
+    Iteration counts add up and the histories are concatenated."""
+    r = run(x0, maxit)
+    used, outer, hists = 0, r.outer, [r.hist]
+    while r.status == OK and used < restarts and r.true_rel > rtol:
+        left = maxit - outer * s
+        if left <= 0:
+            break
+        r = run(r.x, left)
+        used += 1
+        outer += r.outer
+        hists.append(r.hist)
+    r.outer, r.cg_equiv, r.restarts = outer, outer * s, used
+    r.hist = np.concatenate(hists)
+    return r
+
+
+def pcg(op: Operator, b, x0=None, rtol=1e-8, maxit=10000, prec=PREC_JACOBI, restarts=0):
+    """Alg. 1; with restarts > 0, residual replacement by restart (_restarted)."""
+    if restarts > 0:
+        return _restarted(lambda x, m: pcg(op, b, x, rtol, m, prec), x0, rtol, maxit, 1, restarts)
     """Alg. 1 on the oracle operator; returns a Result with x and history."""
     b = np.ascontiguousarray(b, dtype=np.float64)
     x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
@@ -238,9 +262,12 @@ def pcg(op: Operator, b, x0=None, rtol=1e-8, maxit=10000, prec=PREC_JACOBI):
     return _result(res, hist, x)
 
 
-def pfcg(op: Operator, b, x0=None, rtol=1e-8, maxit=10000, prec=PREC_JACOBI):
+def pfcg(op: Operator, b, x0=None, rtol=1e-8, maxit=10000, prec=PREC_JACOBI, restarts=0):
     """Alg. 2 (PFCG) on the oracle operator; returns a Result with x and history.
-    maxit counts every step, the one before the loop included."""
+    maxit counts every step, the one before the loop included.  restarts > 0:
+    residual replacement by restart (_restarted)."""
+    if restarts > 0:
+        return _restarted(lambda x, m: pfcg(op, b, x, rtol, m, prec), x0, rtol, maxit, 1, restarts)
     b = np.ascontiguousarray(b, dtype=np.float64)
     x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
     hist = np.zeros(maxit + 2)
@@ -250,13 +277,17 @@ def pfcg(op: Operator, b, x0=None, rtol=1e-8, maxit=10000, prec=PREC_JACOBI):
 
 
 def sstep(op: Operator, b, s, x0=None, rtol=1e-8, maxit=10000, prec=PREC_JACOBI,
-          fixed_outer=0, trace_cap=0, trace_P=False):
+          fixed_outer=0, trace_cap=0, trace_P=False, restarts=0):
     """Alg. 3 (with Alg. 4-6) on the oracle operator.
 
     ``fixed_outer`` > 0 runs exactly that many outer iterations.  With
     ``trace_cap`` > 0 the per-iteration moments vm, alpha, beta and W (and with
     ``trace_P`` the block [P_i | A P_i] after the update) are returned.
+    ``restarts`` > 0: residual replacement by restart (_restarted).
     """
+    if restarts > 0:
+        return _restarted(lambda x, m: sstep(op, b, s, x, rtol, m, prec), x0, rtol, maxit, s,
+                          restarts)
     b = np.ascontiguousarray(b, dtype=np.float64)
     x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
     outer_cap = fixed_outer if fixed_outer > 0 else (maxit + max(s, 1) - 1) // max(s, 1)
