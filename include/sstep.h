@@ -111,6 +111,16 @@ typedef struct ssp_opts {
                           it is judged (removes its rough, high-residual part);
                           0 = none                                              */
   double warm_omega;   /* damping of those sweeps; 0 = 2/3                      */
+  int restarts;        /* FP64 solves: when the recursive test holds but the
+                          true residual ||b - A x|| exceeds rtol ||b|| (the
+                          recurrences drift from it by rounding, most at large
+                          s), start the method again from the current x, at
+                          most this many times, within the budget of maxit
+                          CG-equivalent steps; 0 = never.  Iteration counts add
+                          up and the residual histories are concatenated (each
+                          run starts with its true residual); see
+                          ssp_get_restarts.  MIXED_IR ignores it: its
+                          refinement loop already ends on the true residual   */
 } ssp_opts;
 
 /* ---- handle ---------------------------------------------------------------- */
@@ -198,8 +208,12 @@ int ssp_mpk(ssp_handle *h, const ssp_matrix *A, const double *r, int s, double *
 int ssp_solve(ssp_handle *h, const ssp_matrix *A, const double *b, double *x, int s,
               double rtol, int maxit, const ssp_opts *opts);
 
-/* Outer iterations and CG-equivalent steps (s * outer) of the last solve. */
+/* Outer iterations and CG-equivalent steps (s * outer) of the last solve
+ * (summed over its restarts). */
 int ssp_get_iterations(const ssp_handle *h, int *outer, int *cg_equiv);
+
+/* Restarts the last solve made (opts.restarts; 0 if none). */
+int ssp_get_restarts(const ssp_handle *h, int *restarts);
 
 /* Outcome of the last solve's warm-start judge (opts.warm_start = 1):
  * *kept = 1 if the given x was used, 0 if it fell back to x = 0, -1 if the

@@ -1010,6 +1010,8 @@ int ssp_solve(ssp_handle *h, const ssp_matrix *A, const double *b, double *x, in
     return fail(h, SSP_EINVAL, "ssp_solve: unknown precision " + std::to_string(precision));
   if (precision == SSP_PRECISION_MIXED_IR && method != SSP_METHOD_SSTEP)
     return fail(h, SSP_EUNSUPPORTED, "ssp_solve: mixed precision is implemented for the s-step method");
+  const int restarts = opts ? opts->restarts : 0;
+  if (restarts < 0) return fail(h, SSP_EINVAL, "ssp_solve: restarts must be >= 0");
   HIPCHK(h, hipSetDevice(h->device));
   h->prof_on = opts && opts->profile;
   h->ev_used = 0;
@@ -1019,6 +1021,7 @@ int ssp_solve(ssp_handle *h, const ssp_matrix *A, const double *b, double *x, in
   }
   h->last_warm_kept = -1;
   h->last_warm_rel0 = NAN;
+  h->last_restarts = 0;
   if (opts && opts->warm_start) {
     if (opts->warm_sweeps < 0 || opts->warm_omega < 0.0 || opts->warm_omega >= 2.0)
       return fail(h, SSP_EINVAL, "ssp_solve: warm_sweeps must be >= 0 and 0 <= warm_omega < 2");
@@ -1027,15 +1030,43 @@ int ssp_solve(ssp_handle *h, const ssp_matrix *A, const double *b, double *x, in
   }
   if (precision == SSP_PRECISION_MIXED_IR)
     return solve_mixed(h, const_cast<ssp_matrix *>(A), b, x, s, rtol, maxit, opts);
-  if (method == SSP_METHOD_PCG) return solve_pcg(h, A, b, x, rtol, maxit, opts);
-  if (method == SSP_METHOD_PFCG) return solve_pfcg(h, A, b, x, rtol, maxit, opts);
-  return solve_sstep(h, A, b, x, s, rtol, maxit, opts);
+  const int sm = method == SSP_METHOD_SSTEP ? s : 1;   // CG-equivalent steps per outer iteration
+  auto run = [&](int budget) {
+    if (method == SSP_METHOD_PCG) return solve_pcg(h, A, b, x, rtol, budget, opts);
+    if (method == SSP_METHOD_PFCG) return solve_pfcg(h, A, b, x, rtol, budget, opts);
+    return solve_sstep(h, A, b, x, s, rtol, budget, opts);
+  };
+  rc = run(maxit);
+  if (restarts > 0 && !(opts && opts->fixed_outer > 0)) {
+    // residual replacement: the recursive test held, the true residual did
+    // not; run again from the current x, whose first residual is the true one
+    int outer = h->last_outer;
+    std::vector<double> hist = h->last_hist;
+    while (rc == SSP_OK && h->last_restarts < restarts && h->last_true_rel > rtol) {
+      const int64_t left = (int64_t)maxit - (int64_t)outer * sm;
+      if (left <= 0) break;
+      rc = run((int)left);
+      if (rc < 0) return rc;
+      h->last_restarts++;
+      outer += h->last_outer;
+      hist.insert(hist.end(), h->last_hist.begin(), h->last_hist.end());
+    }
+    h->last_outer = outer;
+    h->last_hist = hist;
+  }
+  return rc;
 }
 
 int ssp_get_iterations(const ssp_handle *h, int *outer, int *cg_equiv) {
   if (!h) return SSP_EINVAL;
   if (outer) *outer = h->last_outer;
   if (cg_equiv) *cg_equiv = h->last_outer * h->last_s;
+  return SSP_OK;
+}
+
+int ssp_get_restarts(const ssp_handle *h, int *restarts) {
+  if (!h) return SSP_EINVAL;
+  if (restarts) *restarts = h->last_restarts;
   return SSP_OK;
 }
 

@@ -48,6 +48,7 @@ struct ssp_handle {
   int last_outer = 0, last_s = 1;
   double last_true_rel = NAN;
   std::vector<double> last_hist;
+  int last_restarts = 0;           // residual-replacement restarts of the last solve
   int last_warm_kept = -1;         // warm-start judge: 1 kept, 0 fell back, -1 none
   double last_warm_rel0 = NAN;
   // profiling (HIP events around launches)

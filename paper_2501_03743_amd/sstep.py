@@ -38,7 +38,7 @@ EXPORTS = (
     "ssp_autotune_batch", "ssp_net_create", "ssp_net_destroy", "ssp_net_params",
     "ssp_net_forward", "ssp_net_zero_grad", "ssp_net_backward", "ssp_net_loss",
     "ssp_net_adam_step", "ssp_net_get_state", "ssp_net_set_state", "ssp_conv3d",
-    "ssp_conv3d_wgrad", "ssp_net_mfma_selftest", "ssp_get_warm_start",
+    "ssp_conv3d_wgrad", "ssp_net_mfma_selftest", "ssp_get_warm_start", "ssp_get_restarts",
     "ssp_net_loss_h1", "ssp_matrix_csr_form",
 )
 
@@ -66,7 +66,7 @@ class _Opts(C.Structure):
                 ("trace_vm", C.c_void_p), ("trace_alpha", C.c_void_p),
                 ("trace_beta", C.c_void_p), ("trace_W", C.c_void_p),
                 ("warm_start", C.c_int), ("warm_sweeps", C.c_int),
-                ("warm_omega", C.c_double)]
+                ("warm_omega", C.c_double), ("restarts", C.c_int)]
 
 
 _lib = None
@@ -110,6 +110,7 @@ def load():
         "ssp_get_residual_history": (i32, [vp, vp, i32, C.POINTER(i32)]),
         "ssp_get_true_residual": (i32, [vp, C.POINTER(dbl)]),
         "ssp_get_warm_start": (i32, [vp, C.POINTER(i32), C.POINTER(dbl)]),
+        "ssp_get_restarts": (i32, [vp, C.POINTER(i32)]),
         "ssp_get_profile": (i32, [vp, vp, vp]),
         "ssp_solve_batch": (i32, [vp, i32, vp, vp, vp, i32, dbl, i32, C.POINTER(_Opts),
                                   C.POINTER(Tune), vp, vp, vp]),
@@ -170,6 +171,7 @@ class SolveResult:
     profile: Optional[dict] = None
     warm_kept: int = -1          # 1 warm start used, 0 fell back to x0 = 0, -1 none
     warm_rel0: float = float("nan")
+    restarts: int = 0            # residual-replacement restarts made
 
     @property
     def ok(self):
@@ -398,7 +400,7 @@ class Handle:
               max_refine: int = 10, check_every: int = 0, fixed_outer: int = 0,
               profile: bool = False, trace_cap: int = 0,
               warm_start: bool = False, warm_sweeps: int = 0,
-              warm_omega: float = 0.0) -> SolveResult:
+              warm_omega: float = 0.0, restarts: int = 0) -> SolveResult:
         import torch
         _check_dev(b, torch.float64, A.n, "b")
         _check_dev(x, torch.float64, A.n, "x")
@@ -406,7 +408,7 @@ class Handle:
                   max_refine=max_refine, check_every=check_every, fixed_outer=fixed_outer,
                   profile=1 if profile else 0, trace_cap=0,
                   warm_start=1 if warm_start else 0, warm_sweeps=warm_sweeps,
-                  warm_omega=warm_omega)
+                  warm_omega=warm_omega, restarts=restarts)
         trace = None
         if trace_cap > 0:
             trace = dict(vm=np.zeros((trace_cap, 2 * s)), alpha=np.zeros((trace_cap, s)),
@@ -439,9 +441,11 @@ class Handle:
             trace = {k: v[:outer.value] for k, v in trace.items()}
         kept, rel0 = C.c_int(), C.c_double()
         lib.ssp_get_warm_start(self._h, C.byref(kept), C.byref(rel0))
+        nrs = C.c_int()
+        lib.ssp_get_restarts(self._h, C.byref(nrs))
         return SolveResult(status=rc, outer=outer.value, cg_equiv=cge.value, true_rel=tr.value,
                            hist=hist, trace=trace, profile=prof, warm_kept=kept.value,
-                           warm_rel0=rel0.value)
+                           warm_rel0=rel0.value, restarts=nrs.value)
 
     # ---------------------------------------------------------------- network
     def net(self, shape, max_batch: int = 1, seed: int = 0) -> "Net":
