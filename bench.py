@@ -462,6 +462,10 @@ def main():
         t, r = timed(lambda: solve(s=s), reps=2)
         per_s[str(s)] = {"tts_s": t, "outer": r.outer, "status": r.status,
                          "true_rel": r.true_rel}
+    # s = 8 drifts from the true residual; residual replacement by restart
+    t, r = timed(lambda: solve(s=8, restarts=3), reps=2)
+    per_s["8_restarts"] = {"tts_s": t, "outer": r.outer, "status": r.status,
+                           "true_rel": r.true_rel, "restarts": r.restarts}
 
     # 3D 27-point 256^3 (n = 16.8M, 449M stored entries), Jacobi, s = 4, to rtol 1e-10:
     # plain FP64 s-step and standard CG versus the FP32-inner / FP64-refinement form;

@@ -384,10 +384,9 @@ __global__ __launch_bounds__(256) void k_sum_blocks(const float *__restrict__ pa
 // Packs FP32 weights W[27][Ci][Co] into BF16 GEMM operands:
 //   fwd: wf[co][t*Ci + ci]   (k padded to kpf with zeros)
 //   bwd: wb[ci][t*Co + co]   (k padded to kpb with zeros)
-__global__ __launch_bounds__(256) void k_pack(const float *__restrict__ w, int ci_n, int co_n,
-                                              bf16 *__restrict__ wf, int kpf,
-                                              bf16 *__restrict__ wb, int kpb) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void pack_elem(const float *__restrict__ w, int ci_n, int co_n,
+                                          bf16 *__restrict__ wf, int kpf, bf16 *__restrict__ wb,
+                                          int kpb, int64_t i) {
   const int64_t nf = (int64_t)co_n * kpf, nb = (int64_t)ci_n * kpb;
   if (i < nf) {
     const int co = (int)(i / kpf), k = (int)(i % kpf);
@@ -407,6 +406,30 @@ __global__ __launch_bounds__(256) void k_pack(const float *__restrict__ w, int c
     }
     wb[i] = (bf16)v;
   }
+}
+
+__global__ __launch_bounds__(256) void k_pack(const float *__restrict__ w, int ci_n, int co_n,
+                                              bf16 *__restrict__ wf, int kpf,
+                                              bf16 *__restrict__ wb, int kpb) {
+  pack_elem(w, ci_n, co_n, wf, kpf, wb, kpb, (int64_t)blockIdx.x * 256 + threadIdx.x);
+}
+
+// Every layer's packing in one launch (the per-layer launches were mostly
+// launch overhead): element i belongs to the layer L with
+// start[L] <= i < start[L + 1].
+constexpr int kPackLayers = 10;
+struct PackTable {
+  const float *w[kPackLayers];
+  bf16 *wf[kPackLayers], *wb[kPackLayers];
+  int ci[kPackLayers], co[kPackLayers], kpf[kPackLayers], kpb[kPackLayers];
+  int64_t start[kPackLayers + 1];
+};
+__global__ __launch_bounds__(256) void k_pack_all(PackTable t) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= t.start[kPackLayers]) return;
+  int L = 0;
+  while (L + 1 < kPackLayers && i >= t.start[L + 1]) ++L;
+  pack_elem(t.w[L], t.ci[L], t.co[L], t.wf[L], t.kpf[L], t.wb[L], t.kpb[L], i - t.start[L]);
 }
 
 // --------------------------------------------------------------------------
@@ -853,11 +876,23 @@ int ssp_net_forward(ssp_net *n, const float *in, int batch, float *out) {
   if (!n || !in || !out || batch < 1 || batch > n->max_batch) return SSP_EINVAL;
   ssp_handle *h = n->h;
   HIPCHK(h, hipSetDevice(h->device));
-  // BF16 GEMM operands from the FP32 master weights
-  for (int L = 0; L < kLayers; ++L) {
-    const int64_t nf = (int64_t)kDef[L].co * n->kpf[L], nb = (int64_t)kDef[L].ci * n->kpb[L];
-    k_pack<<<nblocks(std::max(nf, nb)), 256, 0, h->stream>>>(
-        n->params + n->w_off[L], kDef[L].ci, kDef[L].co, n->wf[L], n->kpf[L], n->wb[L], n->kpb[L]);
+  // BF16 GEMM operands from the FP32 master weights, all layers in one launch
+  {
+    static_assert(kLayers == kPackLayers, "one packing table entry per layer");
+    PackTable t;
+    t.start[0] = 0;
+    for (int L = 0; L < kLayers; ++L) {
+      const int64_t nf = (int64_t)kDef[L].co * n->kpf[L], nb = (int64_t)kDef[L].ci * n->kpb[L];
+      t.w[L] = n->params + n->w_off[L];
+      t.wf[L] = n->wf[L];
+      t.wb[L] = n->wb[L];
+      t.ci[L] = kDef[L].ci;
+      t.co[L] = kDef[L].co;
+      t.kpf[L] = n->kpf[L];
+      t.kpb[L] = n->kpb[L];
+      t.start[L + 1] = t.start[L] + std::max(nf, nb);
+    }
+    k_pack_all<<<nblocks(t.start[kLayers]), 256, 0, h->stream>>>(t);
     LAUNCHCHK(h);
   }
   Grid3 g[5];
