@@ -184,6 +184,34 @@ def bench_batch(H, count=32, lo=32, hi=160, seed=0):
     return out
 
 
+def bench_paper_1e9(H):
+    """Sec. V-B's weak-scaled problem (64 x 250^3 = 10^9 unknowns, 2101
+    iterations for PFCG and PCGs with s = 1 on 64 GPUs) on one GPU, as the
+    1000^3 cube in stencil form: time to solution of each method, one run
+    each (the solves take seconds, the set-up is excluded)."""
+    import torch
+    N = 1000
+    A = H.matrix_stencil("3d7", (N, N, N))
+    A.set_preconditioner("none")
+    b = torch.ones(N ** 3, dtype=torch.float64, device="cuda")
+    x = torch.zeros_like(b)
+    out = {"workload": "3D 7-point 1000^3 stencil (n=10^9), b=1, no preconditioner, rtol 1e-6",
+           "paper_iterations_64_gpus": 2101}
+    for name, kw in (("pfcg", {"method": "pfcg"}), ("pcg", {"method": "pcg"}),
+                     ("sstep_s4", {"s": 4}), ("sstep_s4_mixed_ir", {"s": 4, "precision": "mixed_ir",
+                                                                  "inner_rtol": 1e-3})):
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = H.solve(A, b, x, rtol=1e-6, maxit=8000, **kw)
+        torch.cuda.synchronize()
+        out[name] = {"tts_s": time.perf_counter() - t0, "status": r.status, "outer": r.outer,
+                     "cg_equiv": r.cg_equiv, "true_rel": r.true_rel}
+        print("[paper-1e9] %s %s" % (name, json.dumps(out[name])), file=sys.stderr, flush=True)
+    A.close()
+    return out
+
+
 def bench_warmstart(H, n_train=2000, n_eval=200, side=96, epochs=40, lr=2e-3, batch=4,
                     log=None, sweeps=16):
     """The learned warm start on -div(k grad u) = f at side^3: log k a Gaussian
@@ -273,6 +301,10 @@ def main():
     ap.add_argument("--csr256-outer", type=int, default=0,
                     help="only the 256^3 7-point CSR solve for this many outer iterations "
                          "(s = 4, no stopping test): a short target for counter runs")
+    ap.add_argument("--paper-1e9", action="store_true",
+                    help="only the paper's largest problem on one GPU: 3D 7-point 1000^3 "
+                         "(10^9 unknowns, stencil form), b = 1, no preconditioner, rtol 1e-6; "
+                         "PFCG, standard PCG and the s-step form (about 3 minutes)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only a plain 1 GiB device-to-device copy, three times (the "
                          "reference for the FETCH_SIZE / WRITE_SIZE counter scale)")
@@ -296,6 +328,9 @@ def main():
         print(json.dumps({"copy_bytes": src.numel() * 8, "copies": 3}))
         return
     H = sstep.Handle(0)
+    if args.paper_1e9:
+        print(json.dumps({"paper_1e9": bench_paper_1e9(H)}))
+        return
     if args.csr256_outer > 0:
         N3 = 256
         A3 = H.matrix_csr_from_stencil("3d7", (N3, N3, N3))
