@@ -108,6 +108,21 @@ __device__ __forceinline__ XcdSched xcd_sched(int64_t items, int64_t piece, int 
   return s;
 }
 
+// Loads and stores of data that is not read again soon (the updates'
+// stream-once columns and vectors).  The non-temporal hint keeps them from
+// displacing what the next kernels read again from the caches: a matrix that
+// fits the 256 MB memory-side cache then stays there from one iteration to
+// the next (128^3 7-point CSR: the first matrix power after the update
+// 50 -> 32 us).  Values are unchanged; only the cache policy differs.
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T *p) {
+  return __builtin_nontemporal_load(p);
+}
+template <typename T>
+__device__ __forceinline__ void st_stream(T *p, T v) {
+  __builtin_nontemporal_store(v, p);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);

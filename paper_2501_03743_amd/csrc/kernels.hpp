@@ -568,12 +568,12 @@ __device__ __forceinline__ double update_rows(const UpdateCoef<S, T> &c, int64_t
     T azs[S];
 #pragma unroll
     for (int j = 0; j < S; ++j) {
-      azs[j] = Pc[(int64_t)(S + j) * ld + i];
+      azs[j] = ld_stream(&Pc[(int64_t)(S + j) * ld + i]);
       ap[j] = (double)azs[j];
     }
     if (zc == T(0)) {
 #pragma unroll
-      for (int j = 0; j < S; ++j) p[j] = (double)Pc[(int64_t)j * ld + i];
+      for (int j = 0; j < S; ++j) p[j] = (double)ld_stream(&Pc[(int64_t)j * ld + i]);
     } else {
       p[0] = (double)(zc * r0);
 #pragma unroll
@@ -583,8 +583,8 @@ __device__ __forceinline__ double update_rows(const UpdateCoef<S, T> &c, int64_t
       double po[S], apo[S];
 #pragma unroll
       for (int l = 0; l < S; ++l) {
-        po[l] = (double)Po[(int64_t)l * ld + i];
-        apo[l] = (double)Po[(int64_t)(S + l) * ld + i];
+        po[l] = (double)ld_stream(&Po[(int64_t)l * ld + i]);
+        apo[l] = (double)ld_stream(&Po[(int64_t)(S + l) * ld + i]);
       }
 #pragma unroll
       for (int j = 0; j < S; ++j) {
@@ -597,15 +597,15 @@ __device__ __forceinline__ double update_rows(const UpdateCoef<S, T> &c, int64_t
           b += u;
         }
         const T as = (T)a, bs = (T)b;
-        Pc[(int64_t)j * ld + i] = as;
-        Pc[(int64_t)(S + j) * ld + i] = bs;
+        st_stream(&Pc[(int64_t)j * ld + i], as);
+        st_stream(&Pc[(int64_t)(S + j) * ld + i], bs);
         p[j] = (double)as;
         ap[j] = (double)bs;
       }
     } else if (zc != T(0)) {
       // k = 0: P = Z must be stored for the next iteration's P_old beta
 #pragma unroll
-      for (int j = 0; j < S; ++j) Pc[(int64_t)j * ld + i] = (T)p[j];
+      for (int j = 0; j < S; ++j) st_stream(&Pc[(int64_t)j * ld + i], (T)p[j]);
     }
     double dx = 0.0, dr = 0.0;
 #pragma unroll
@@ -615,9 +615,9 @@ __device__ __forceinline__ double update_rows(const UpdateCoef<S, T> &c, int64_t
       const double u = ap[j] * c.alpha[j];
       dr += u;
     }
-    const T xi = (T)((double)x[i] + dx);
+    const T xi = (T)((double)ld_stream(&x[i]) + dx);
     const T ri = (T)((double)r0 - dr);
-    x[i] = xi;
+    st_stream(&x[i], xi);
     r[i] = ri;
     if (zc == T(0)) Po[i] = pc.apply(i, ri);
     part += (double)ri * (double)ri;
@@ -680,11 +680,13 @@ static __global__ __attribute__((unused)) __launch_bounds__(kWG) void k_pcg_upda
   int64_t lo, hi;
   block_chunk(n, logical_block(), gridDim.x, lo, hi);
   for (int64_t i = lo + threadIdx.x; i < hi; i += kWG) {
+    // x and s = A p are not read again soon (non-temporal); p and r are
+    // read by the next kernels
     const double ap = a * p[i];
-    const double xi = x[i] + ap;
-    const double as = a * sv[i];
+    const double xi = ld_stream(&x[i]) + ap;
+    const double as = a * ld_stream(&sv[i]);
     const double ri = r[i] - as;
-    x[i] = xi;
+    st_stream(&x[i], xi);
     r[i] = ri;
     const double ui = pc.apply(i, ri);
     ur += ui * ri;
@@ -733,6 +735,8 @@ static __global__ __attribute__((unused)) __launch_bounds__(kWG) void k_pfcg_upd
   for (int64_t b0 = sc.first; b0 < sc.end; b0 += sc.stride) {
     const int64_t b1 = b0 + kWG < sc.end ? b0 + kWG : sc.end;
     for (int64_t i = b0 + threadIdx.x; i < b1; i += kWG) {
+      // plain loads and stores: PFCG's five vectors (84 MB at 128^3) fit the
+      // memory-side cache, and non-temporal hints here measured slower
       const double ri = r[i];
       const double ui = u ? u[i] : pc.dc * ri;
       const double gp = g * p[i];
