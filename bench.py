@@ -184,6 +184,36 @@ def bench_batch(H, count=32, lo=32, hi=160, seed=0):
     return out
 
 
+def bench_net_steps(H, steps, side=96, batch=4):
+    """Training steps and batch-1 forwards of the warm-start network on random
+    inputs (timing and counter target; the values are irrelevant here)."""
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    net = H.net((side, side, side), max_batch=batch, seed=0)
+    inp = torch.randn((batch, side, side, side, 2), generator=g, device="cuda")
+    tgt = torch.randn((batch, side, side, side), generator=g, device="cuda")
+    y = torch.empty_like(tgt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        net.forward(inp, y)
+        _, dy = net.loss_h1(y, tgt, 1e-3)
+        net.zero_grad()
+        net.backward(dy)
+        net.adam_step(1e-3)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    one = inp[:1].contiguous()
+    for _ in range(steps):
+        net.forward(one)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    net.close()
+    return {"side": side, "batch": batch, "steps": steps,
+            "train_step_ms": 1e3 * (t1 - t0) / steps, "forward_batch1_ms": 1e3 * (t2 - t1) / steps}
+
+
 def bench_paper_1e9(H):
     """Sec. V-B's weak-scaled problem (64 x 250^3 = 10^9 unknowns, 2101
     iterations for PFCG and PCGs with s = 1 on 64 GPUs) on one GPU, as the
@@ -305,6 +335,10 @@ def main():
                     help="only the paper's largest problem on one GPU: 3D 7-point 1000^3 "
                          "(10^9 unknowns, stencil form), b = 1, no preconditioner, rtol 1e-6; "
                          "PFCG, standard PCG and the s-step form (about 3 minutes)")
+    ap.add_argument("--net-steps", type=int, default=0,
+                    help="only this many training steps of the warm-start network at 96^3, "
+                         "batch 4 (forward, energy loss, backward, Adam) and as many batch-1 "
+                         "forwards: a short target for kernel-trace and MFMA counter runs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only a plain 1 GiB device-to-device copy, three times (the "
                          "reference for the FETCH_SIZE / WRITE_SIZE counter scale)")
@@ -328,6 +362,9 @@ def main():
         print(json.dumps({"copy_bytes": src.numel() * 8, "copies": 3}))
         return
     H = sstep.Handle(0)
+    if args.net_steps > 0:
+        print(json.dumps({"net_steps": bench_net_steps(H, args.net_steps)}))
+        return
     if args.paper_1e9:
         print(json.dumps({"paper_1e9": bench_paper_1e9(H)}))
         return
