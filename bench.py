@@ -437,6 +437,7 @@ def main():
 
     cg_t, cg_r = timed(lambda: solve(method="pcg"))
     pf_t, pf_r = timed(lambda: solve(method="pfcg"))
+    mx_t, mx_r = timed(lambda: solve(precision="mixed_ir"))
     As = H.matrix_stencil("3d7", (N, N, N))
     def solve_st(**kw):
         x.zero_()
@@ -623,6 +624,8 @@ def main():
             "sstep_stencil_tts_s": st_t, "sstep_stencil_outer": st_r.outer,
             "pcg_stencil_tts_s": stcg_t, "pcg_stencil_iterations": stcg_r.outer,
             "pfcg_csr_tts_s": pf_t, "pfcg_csr_iterations": pf_r.outer,
+            "sstep_mixed_ir_csr_tts_s": mx_t, "sstep_mixed_ir_csr_outer": mx_r.outer,
+            "sstep_mixed_ir_csr_true_rel": mx_r.true_rel,
             "pfcg_stencil_tts_s": stpf_t, "pfcg_stencil_iterations": stpf_r.outer,
             "sstep_csr_by_s": per_s,
             "spmv": spmv,

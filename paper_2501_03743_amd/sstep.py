@@ -401,6 +401,16 @@ class Handle:
               profile: bool = False, trace_cap: int = 0,
               warm_start: bool = False, warm_sweeps: int = 0,
               warm_omega: float = 0.0, restarts: int = 0) -> SolveResult:
+        """ssp_solve: A x = b on the device (x holds x0 on entry, the solution on
+        return).  method: "sstep" (Alg. 3-6, block size s), "pcg" (Alg. 1) or
+        "pfcg" (Alg. 2); precision: "fp64" or "mixed_ir" (s-step only: FP32
+        inner solves to inner_rtol inside FP64 refinement); fixed_outer > 0
+        runs exactly that many outer iterations; restarts > 0 re-runs an FP64
+        method from x while its true residual misses rtol; warm_start judges
+        the given x (after warm_sweeps damped Jacobi sweeps) and falls back to
+        x = 0 when ||b - A x|| >= ||b||.  Returns the status (0 converged,
+        1 not converged, 2 breakdown), iteration counts, residual history and
+        true residual; raises SspError on invalid arguments."""
         import torch
         _check_dev(b, torch.float64, A.n, "b")
         _check_dev(x, torch.float64, A.n, "x")
