@@ -125,6 +125,7 @@ __device__ __forceinline__ LastPre<S> epi_pre(const EpiMpkLast<S, T> &e, int64_t
 template <int S, typename T>
 __device__ __forceinline__ void epi_row(const EpiMpkLast<S, T> &e, int64_t i, T v,
                                         const LastPre<S> &p, double *part) {
+#pragma clang fp contract(off)
   e.az[i] = v;
   const double vi = (double)v;
 #pragma unroll
@@ -204,6 +205,7 @@ struct EpiPcgSpmv {
   const double *p;
   double *sv;
   __device__ __forceinline__ void row(int64_t i, double v, double *part) const {
+#pragma clang fp contract(off)
     sv[i] = v;
     part[0] += p[i] * v;
   }
