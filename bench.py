@@ -344,7 +344,7 @@ def main():
                          "reference for the FETCH_SIZE / WRITE_SIZE counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (no sharding or collectives); "
+        print("bench.py: the library runs on one GPU (no sharding or collectives); "
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
