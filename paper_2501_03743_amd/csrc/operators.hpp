@@ -202,15 +202,16 @@ __device__ __forceinline__ int64_t sell_entry(int64_t off, int w, int u, int lan
 // than the memory-side cache, XCD-interleaved pieces (an XCD's workgroups
 // then stream neighbouring slices together, which keeps HBM pages and the
 // gathered x shared; measured 8 % faster at 256^3, 2 % slower on a
-// cache-resident 128^3 matrix).  The headers
-// (offset, width) of up to 64 of its slices are read once, one per lane, and
-// broadcast when a slice is processed.  The column indices of the next
-// slice's first U entries are loaded right after the current slice's gathers
-// and values, so they are in flight while the current slice is summed and
-// stored, and the next gathers can be issued at once.  Only entries inside
-// the width with a column >= 0 enter a sum (the others gather the row's own
-// x): each row's sum has the same terms, order and rounding as the CSR
-// product.
+// cache-resident 128^3 matrix).  The headers (offset, width) of up to 64 of
+// a wavefront's slices are read once, one per lane, and broadcast when a
+// slice is processed.  The column indices of the next slice's first U
+// entries are loaded right after the current slice's gathers and values, so
+// they are in flight while the current slice is summed and stored, and the
+// next gathers can be issued at once (prefetching the later passes of wide
+// slices as well measured no faster on the 27-point matrix).  Only entries
+// inside the width with a column >= 0 enter a sum (the others gather the
+// row's own x): each row's sum has the same terms, order and rounding as the
+// CSR product.
 template <typename T, class Pre, class F>
 __device__ __forceinline__ void sell_rows(const CsrArgs<T> &A, const T *__restrict__ x, Pre &&pre,
                                           F &&f, T xs) {
