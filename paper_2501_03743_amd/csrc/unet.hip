@@ -178,14 +178,26 @@ __global__ __launch_bounds__(256) void k_conv_tiled(const bf16 *__restrict__ in,
                                                     bf16 *__restrict__ out_b) {
   constexpr int HX = CTX + 2, HY = CTY + 2, HZ = CTZ + 2;
   extern __shared__ __align__(16) bf16 s_in[];
-  __shared__ int s_tap[512];
-  __shared__ int s_ci[512];
+  // per 8-wide k group: the LDS offset of its tap and channel relative to a
+  // lane's own point (negative for taps behind it; kPadOff for the zero
+  // padding past 27 taps), so the inner loop does no index arithmetic
+  constexpr int kPadOff = -(1 << 30);
+  __shared__ int s_off[512];
   const int nk8 = kp / 8;
   for (int i = threadIdx.x; i < nk8; i += 256) {
     const int k = i * 8;
     const int t = k / cin;
-    s_tap[i] = t;
-    s_ci[i] = k - t * cin;
+    int off = kPadOff;
+    if (t < 27) {
+      int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+      if (MODE == 1) {
+        dz = -dz;
+        dy = -dy;
+        dx = -dx;
+      }
+      off = ((dz * HY + dy) * HX + dx) * cin + (k - t * cin);
+    }
+    s_off[i] = off;
   }
   const int ntx = (g.W + CTX - 1) / CTX, nty = (g.H + CTY - 1) / CTY, ntz = (g.D + CTZ - 1) / CTZ;
   int64_t bi = blockIdx.x;
@@ -210,42 +222,53 @@ __global__ __launch_bounds__(256) void k_conv_tiled(const bf16 *__restrict__ in,
   __syncthreads();
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int m = lane % 16, gq = lane / 16;
-  int rz[2], ry[2];
+  int rz[2], ry[2], base[2];
 #pragma unroll
   for (int mt = 0; mt < 2; ++mt) {
     const int r = wave * 2 + mt;   // 0..7: (z, y) row of the block
     rz[mt] = r / CTY;
     ry[mt] = r % CTY;
+    base[mt] = (((rz[mt] + 1) * HY + (ry[mt] + 1)) * HX + (m + 1)) * cin;   // the lane's point
   }
   f32x4 acc[2][NS];
 #pragma unroll
   for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
     for (int n = 0; n < NS; ++n) acc[mt][n] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int kc = 0; kc < kp; kc += 32) {
-    const int i8 = (kc >> 3) + gq;
-    const int t = s_tap[i8];
-    bf16x8 a[2] = {zero8, zero8};
-    if (t < 27) {
-      int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
-      if (MODE == 1) {
-        dz = -dz;
-        dy = -dy;
-        dx = -dx;
-      }
-      const int c0 = s_ci[i8];
+  // KU k chunks of 32 per step: every offset, weight and operand load of the
+  // step is issued before its products, so one round trip serves 2 KU NS
+  // matrix-core operations (chunks past kp re-read the last one and are
+  // skipped, a uniform test)
+  constexpr int KU = 4;
+  const bf16 *wl = wt + (int64_t)m * kp + gq * 8;   // this lane's weight row, n = 0
+  for (int kc = 0; kc < kp; kc += 32 * KU) {
+    int off[KU];
+    bf16x8 w[KU][NS], a[KU][2];
 #pragma unroll
-      for (int mt = 0; mt < 2; ++mt) {
-        const int pi = ((rz[mt] + 1 + dz) * HY + (ry[mt] + 1 + dy)) * HX + (m + 1 + dx);
-        a[mt] = *(const bf16x8 *)(s_in + (int64_t)pi * cin + c0);
-      }
+    for (int u = 0; u < KU; ++u) {
+      const int k = kc + 32 * u < kp ? kc + 32 * u : kp - 32;
+      off[u] = s_off[(k >> 3) + gq];
+#pragma unroll
+      for (int n = 0; n < NS; ++n) w[u][n] = *(const bf16x8 *)(wl + (int64_t)n * 16 * kp + k);
     }
 #pragma unroll
-    for (int n = 0; n < NS; ++n) {
-      const bf16x8 w = *(const bf16x8 *)(wt + (int64_t)(n * 16 + m) * kp + kc + gq * 8);
+    for (int u = 0; u < KU; ++u)
 #pragma unroll
-      for (int mt = 0; mt < 2; ++mt)
-        acc[mt][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], w, acc[mt][n], 0, 0, 0);
+      for (int mt = 0; mt < 2; ++mt) {
+        // padding groups read the lane's own point (always staged) and use zero
+        const bool pad = off[u] == kPadOff;
+        const bf16x8 v = *(const bf16x8 *)(s_in + base[mt] + (pad ? 0 : off[u]));
+        a[u][mt] = pad ? zero8 : v;
+      }
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+      if (kc + 32 * u < kp) {
+#pragma unroll
+        for (int n = 0; n < NS; ++n)
+#pragma unroll
+          for (int mt = 0; mt < 2; ++mt)
+            acc[mt][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u][mt], w[u][n], acc[mt][n], 0, 0, 0);
+      }
     }
   }
   const int cout = NS * 16;
