@@ -104,41 +104,51 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const bf16 *__restrict__ in, 
 #pragma unroll
   for (int n = 0; n < NS; ++n) acc[n] = f32x4{0.f, 0.f, 0.f, 0.f};
   const bf16x8 zero8 = {};
-  for (int kc = 0; kc < kp; kc += 32) {
-    const int i8 = (kc >> 3) + g;
-    const int t = s_tap[i8];
-    bf16x8 a = zero8;
-    if (valid && t < 27) {
+  // KU k chunks per step: every gather and weight load of the step is issued
+  // before its matrix-core operations.  A tap outside the grid, the padding
+  // past 27 taps and a point past the end read element ci of point 0 (always
+  // present) and use zero instead, so no load is behind a branch.
+  constexpr int KU = 4;
+  for (int kc = 0; kc < kp; kc += 32 * KU) {
+    bf16x8 a[KU], w[KU][NS];
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+      const int k = kc + 32 * u < kp ? kc + 32 * u : kp - 32;
+      const int i8 = (k >> 3) + g;
+      const int t = s_tap[i8];
       const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
       int qz, qy, qx;
-      bool ok;
+      bool ok = valid && t < 27;
       if (MODE == 0) {
         qz = stride * z + dz;
         qy = stride * y + dy;
         qx = stride * x + dx;
-        ok = true;
       } else {
         qz = z - dz;
         qy = y - dy;
         qx = x - dx;
-        ok = true;
         if (stride == 2) {
-          ok = ((qz | qy | qx) & 1) == 0;
+          ok = ok && ((qz | qy | qx) & 1) == 0;
           qz >>= 1;
           qy >>= 1;
           qx >>= 1;
         }
       }
       ok = ok && qz >= 0 && qz < gi.D && qy >= 0 && qy < gi.H && qx >= 0 && qx < gi.W;
-      if (ok) {
-        const int64_t q = encode(b, qz, qy, qx, gi);
-        a = *(const bf16x8 *)(in + q * cin + s_ci[i8]);
-      }
+      const int64_t q = ok ? encode(b, qz, qy, qx, gi) : 0;
+      const bf16x8 v = *(const bf16x8 *)(in + q * cin + s_ci[i8]);
+      a[u] = ok ? v : zero8;
+#pragma unroll
+      for (int n = 0; n < NS; ++n)
+        w[u][n] = *(const bf16x8 *)(wt + (int64_t)(n * 16 + m) * kp + k + g * 8);
     }
 #pragma unroll
-    for (int n = 0; n < NS; ++n) {
-      const bf16x8 w = *(const bf16x8 *)(wt + (int64_t)(n * 16 + m) * kp + kc + g * 8);
-      acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w, acc[n], 0, 0, 0);
+    for (int u = 0; u < KU; ++u) {
+      if (kc + 32 * u < kp) {
+#pragma unroll
+        for (int n = 0; n < NS; ++n)
+          acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u], w[u][n], acc[n], 0, 0, 0);
+      }
     }
   }
   const int cout = NS * 16;
