@@ -106,9 +106,10 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const bf16 *__restrict__ in, 
   const bf16x8 zero8 = {};
   // KU k chunks per step: every gather and weight load of the step is issued
   // before its matrix-core operations.  A tap outside the grid, the padding
-  // past 27 taps and a point past the end read element ci of point 0 (always
-  // present) and use zero instead, so no load is behind a branch.
-  constexpr int KU = 4;
+  // past 27 taps and a point past the end load nothing and use zero (for
+  // the stride-2 input gradient most taps are such).  Fewer chunks for the
+  // wide input gradients (registers; measured).
+  constexpr int KU = (MODE == 1 && NS >= 3) ? 2 : 4;
   for (int kc = 0; kc < kp; kc += 32 * KU) {
     bf16x8 a[KU], w[KU][NS];
 #pragma unroll
@@ -135,9 +136,8 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const bf16 *__restrict__ in, 
         }
       }
       ok = ok && qz >= 0 && qz < gi.D && qy >= 0 && qy < gi.H && qx >= 0 && qx < gi.W;
-      const int64_t q = ok ? encode(b, qz, qy, qx, gi) : 0;
-      const bf16x8 v = *(const bf16x8 *)(in + q * cin + s_ci[i8]);
-      a[u] = ok ? v : zero8;
+      a[u] = zero8;
+      if (ok) a[u] = *(const bf16x8 *)(in + encode(b, qz, qy, qx, gi) * cin + s_ci[i8]);
 #pragma unroll
       for (int n = 0; n < NS; ++n)
         w[u][n] = *(const bf16x8 *)(wt + (int64_t)(n * 16 + m) * kp + k + g * 8);
@@ -248,8 +248,8 @@ __global__ __launch_bounds__(256) void k_conv_tiled(const bf16 *__restrict__ in,
   // KU k chunks of 32 per step: every offset, weight and operand load of the
   // step is issued before its products, so one round trip serves 2 KU NS
   // matrix-core operations (chunks past kp re-read the last one and are
-  // skipped, a uniform test)
-  constexpr int KU = 4;
+  // skipped, a uniform test); fewer chunks for wide outputs (registers)
+  constexpr int KU = NS >= 3 ? 2 : 4;
   const bf16 *wl = wt + (int64_t)m * kp + gq * 8;   // this lane's weight row, n = 0
   for (int kc = 0; kc < kp; kc += 32 * KU) {
     int off[KU];
