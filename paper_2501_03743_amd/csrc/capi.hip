@@ -104,6 +104,7 @@ int64_t block_ld(int64_t n, int64_t align, int64_t elem_bytes) {
 int ensure_workspace(ssp_handle *h, int64_t n, int s, int hist_need, bool pcg) {
   Workspace &w = h->ws;
   if (!w.partials) HIPCHK(h, hipMalloc(&w.partials, sizeof(double) * kGridMax * 2 * kSMax));
+  if (!w.partials_rr) HIPCHK(h, hipMalloc(&w.partials_rr, sizeof(double) * kGridMax));
   if (n > w.n || s > w.s) {
     hfree_t(w.P1);
     hfree_t(w.P2);
@@ -472,7 +473,7 @@ int solve_sstep(ssp_handle *h, const ssp_matrix *A, const double *b, double *x, 
     const int m = std::min(every, outer_max - k);
     for (int i = 0; i < m; ++i, ++k) {
       h->prof_iter = k;
-      rc = step(h, A, B, k);
+      rc = step(h, A, B, k, i == 0, i == m - 1);
       if (rc) return rc;
     }
     h->prof_iter = -1;
@@ -644,7 +645,7 @@ int solve_mixed(ssp_handle *h, ssp_matrix *A, const double *b, double *x, int s,
     while (k < inner_max && h->h_read->status == ST_RUNNING) {
       const int m = std::min(every, inner_max - k);
       for (int i = 0; i < m; ++i, ++k) {
-        rc = step(h, A, B, k);
+        rc = step(h, A, B, k, i == 0, i == m - 1);
         if (rc) return rc;
       }
       rc = read_state(h, false);
@@ -724,6 +725,7 @@ int ssp_destroy(ssp_handle *h) {
   hfree_t(w.r32);
   hfree_t(w.d32);
   hfree_t(w.partials);
+  hfree_t(w.partials_rr);
   hfree_t(w.hist);
   hfree_t(h->st);
   if (h->batch_mem) (void)hipFree(h->batch_mem);

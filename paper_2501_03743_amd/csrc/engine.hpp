@@ -30,6 +30,7 @@ struct Workspace {
   float *Q1 = nullptr, *Q2 = nullptr;       // FP32 blocks of the inner solves
   float *r32 = nullptr, *d32 = nullptr;
   double *partials = nullptr;              // kGridMax x 2*kSMax
+  double *partials_rr = nullptr;           // kGridMax: the block update's ||r||^2
   double *hist = nullptr;
   int hist_cap = 0;
 };
@@ -264,9 +265,16 @@ struct IterBufs {
 
 // One outer iteration of the s-step method (Alg. 3): s matrix-power
 // launches (Alg. 4; the last fused with Alg. 5 and followed by the s x s
-// solve of Alg. 6 on the GPU) and the fused block update.
+// solve of Alg. 6 on the GPU) and the fused block update.  Within a batch of
+// iterations enqueued between two host polls, the stopping test of an
+// update runs in the next iteration's last-power finalisation (before its
+// s x s solve, which it skips once the test holds); only the batch's last
+// update gets a finalisation launch of its own, so the polled status is
+// always current.  The powers enqueued after a converging update run
+// without effect on x and r, as the kernels after the stop always did.
 template <int S, typename T>
-int sstep_iteration(ssp_handle *h, const ssp_matrix *A, const IterBufs<T> &B, int k) {
+int sstep_iteration(ssp_handle *h, const ssp_matrix *A, const IterBufs<T> &B, int k,
+                    bool first_in_batch, bool last_in_batch) {
   T *Pc = (k % 2 == 0) ? B.P2 : B.P1;   // Alg. 3: even k fills P2, odd k fills P1
   T *Po = (k % 2 == 0) ? B.P1 : B.P2;
   T *tag = nullptr;
@@ -289,15 +297,20 @@ int sstep_iteration(ssp_handle *h, const ssp_matrix *A, const IterBufs<T> &B, in
       rc = launch_op<T>(h, A, zin,
                         EpiMpk<T>{az, zc == T(0) ? Pc + (int64_t)j * B.ld : nullptr, pc}, 0, xs);
     else
-      rc = launch_op<T>(h, A, zin, EpiMpkLast<S, T>{az, Pc, B.ld, B.r, 1, zc}, 1, xs);
+      rc = launch_op<T>(h, A, zin,
+                        EpiMpkLast<S, T>{az, Pc, B.ld, B.r, 1, zc,
+                                         first_in_batch ? nullptr : h->ws.partials_rr,
+                                         grid_rows(A->n), h->ws.hist},
+                        1, xs);
     if (rc) return rc;
   }
   const int G = grid_rows(A->n);
   prof_begin(h, 2);
   k_update<S, T><<<G, kWG, 0, h->stream>>>(A->n, B.ld, Pc, Po, B.x, B.r, pc, zc, h->st,
-                                            h->ws.partials);
-  k_finalize<FinUpdate><<<1, kWG, 0, h->stream>>>(FinUpdate{h->ws.hist}, h->st, h->ws.partials,
-                                                  G);
+                                            h->ws.partials_rr);
+  if (last_in_batch)
+    k_finalize<FinUpdate><<<1, kWG, 0, h->stream>>>(FinUpdate{h->ws.hist}, h->st,
+                                                    h->ws.partials_rr, G);
   prof_end(h);
   LAUNCHCHK(h);
   return SSP_OK;
@@ -323,7 +336,7 @@ int mpk_only(ssp_handle *h, const ssp_matrix *A, const double *r, double *P, int
 }
 
 template <typename T>
-using iter_fn = int (*)(ssp_handle *, const ssp_matrix *, const IterBufs<T> &, int);
+using iter_fn = int (*)(ssp_handle *, const ssp_matrix *, const IterBufs<T> &, int, bool, bool);
 using mpk_fn = int (*)(ssp_handle *, const ssp_matrix *, const double *, double *, int64_t);
 
 // Defined in inst_f64.hip (s = 1..16) and inst_f32.hip (s = 1..8);

@@ -56,6 +56,19 @@ struct EpiMpk {
 // Last power j = s, fused with Alg. 5: AZ(:,s) = A Z(:,s) and the partial
 // sums of vm(a) = Z(:,a)^T r and vm(s+a) = Z(:,a)^T AZ(:,s), a = 1..s, in
 // FP64 (FP32 products are exact in FP64).  Finalised by the s x s solve.
+// After a block update: ||r||^2 = rr, history entry, stopping test, k += 1
+// (thread 0).
+__device__ __forceinline__ void fin_update(DevState *st, double rr, double *hist) {
+  const int kk = st->k + 1;
+  st->rr = rr;
+  st->k = kk;
+  const double rn = sqrt(rr), bn = sqrt(st->bb);
+  if (kk < st->hist_cap) hist[kk] = rn / bn;
+  const bool conv = rn <= st->rtol * bn;
+  if (!st->fixed && conv) st->status = ST_CONVERGED;
+  else if (kk >= st->outer_max) st->status = (st->fixed && conv) ? ST_CONVERGED : ST_MAXIT;
+}
+
 template <int S, typename T>
 struct EpiMpkLast {
   static constexpr int NP = 2 * S;
@@ -67,6 +80,11 @@ struct EpiMpkLast {
   int solve;        // 0: only store vm (the stand-alone Alg. 4 + Alg. 5 call)
   T zc;             // 0: Z stored; else the constant Jacobi scaling c, with
                     // Z(:,1) = c r and Z(:,a) = c AZ(:,a-1) formed here
+  // the previous block update's ||r||^2 partials, finished here first (its
+  // stopping test) instead of by a launch of their own; nullptr: none
+  const double *rr_part;
+  int rr_G;
+  double *hist;
   __device__ __forceinline__ void row(int64_t i, T v, double *part) const {
 #pragma clang fp contract(off)
     az[i] = v;
@@ -83,6 +101,13 @@ struct EpiMpkLast {
     }
   }
   __device__ __forceinline__ void finish(DevState *st, const double *tot) const {
+    if (rr_part) {   // uniform
+      double rr[1];
+      reduce_partials<1>(rr_part, rr_G, rr);
+      if (threadIdx.x == 0) fin_update(st, rr[0], hist);
+      __syncthreads();
+      if (st->status != ST_RUNNING) return;   // the same value for every thread
+    }
     if (solve) {
       small_solve_t<S>(st, tot);
     } else if (threadIdx.x < NP) {
@@ -653,17 +678,7 @@ struct FinUpdate {
   static constexpr bool kCheck = true;
   double *hist;
   __device__ __forceinline__ void finish(DevState *st, const double *tot) const {
-    if (threadIdx.x == 0) {
-      const double rr = tot[0];
-      const int kk = st->k + 1;
-      st->rr = rr;
-      st->k = kk;
-      const double rn = sqrt(rr), bn = sqrt(st->bb);
-      if (kk < st->hist_cap) hist[kk] = rn / bn;
-      const bool conv = rn <= st->rtol * bn;
-      if (!st->fixed && conv) st->status = ST_CONVERGED;
-      else if (kk >= st->outer_max) st->status = (st->fixed && conv) ? ST_CONVERGED : ST_MAXIT;
-    }
+    if (threadIdx.x == 0) fin_update(st, tot[0], hist);
   }
 };
 
