@@ -564,15 +564,21 @@ int solve_pfcg(ssp_handle *h, const ssp_matrix *A, const double *b, double *x, d
   if (rc) return rc;
   while (k < outer_max && h->h_read->status == ST_RUNNING) {
     const int m = std::min(every, outer_max - k);
+    // within a batch, a step's stopping test runs in the next step's
+    // operator-pass finalisation; the batch's last step has its own
     for (int i = 0; i < m; ++i, ++k) {
       h->prof_iter = k;
-      rc = launch_op<double>(h, A, u ? u : w.r, EpiPfcgSpmv{w.r, u, sv, wv, pc.dc}, 0,
-                             u ? 1.0 : pc.dc);
+      rc = launch_op<double>(
+          h, A, u ? u : w.r,
+          EpiPfcgSpmv{w.r, u, sv, wv, pc.dc, i == 0 ? nullptr : w.partials_rr, G, w.hist}, 0,
+          u ? 1.0 : pc.dc);
       if (rc) return rc;
       prof_begin(h, 2);
       k_pfcg_update<<<G, kWG, 0, h->stream>>>(A->n, x, w.r, p, sv, wv, u, pc, h->st,
-                                              w.partials);
-      k_finalize<FinUpdate><<<1, kWG, 0, h->stream>>>(FinUpdate{w.hist}, h->st, w.partials, G);
+                                              w.partials_rr);
+      if (i == m - 1)
+        k_finalize<FinUpdate><<<1, kWG, 0, h->stream>>>(FinUpdate{w.hist}, h->st, w.partials_rr,
+                                                        G);
       prof_end(h);
       LAUNCHCHK(h);
     }

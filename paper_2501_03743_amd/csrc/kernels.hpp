@@ -284,6 +284,11 @@ struct EpiPfcgSpmv {
   const double *r, *u, *sv;   // u: stored B^-1 r, or nullptr (constant c)
   double *w;
   double c;
+  // the previous update's ||r||^2 partials, finished here first (its
+  // stopping test) instead of by a launch of their own; nullptr: none
+  const double *rr_part;
+  int rr_G;
+  double *hist;
   __device__ __forceinline__ void row(int64_t i, double v, double *part) const {
 #pragma clang fp contract(off)
     w[i] = v;
@@ -295,6 +300,13 @@ struct EpiPfcgSpmv {
   }
   __device__ __forceinline__ void finish(DevState *st, const double *tot) const {
 #pragma clang fp contract(off)
+    if (rr_part) {   // uniform
+      double rr[1];
+      reduce_partials<1>(rr_part, rr_G, rr);
+      if (threadIdx.x == 0) fin_update(st, rr[0], hist);
+      __syncthreads();
+      if (st->status != ST_RUNNING) return;   // the same value for every thread
+    }
     if (threadIdx.x == 0) {
       const double alpha = tot[0], beta = tot[1], gamma = tot[2];
       const double rho_prev = st->rho;
