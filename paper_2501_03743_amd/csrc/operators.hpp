@@ -212,7 +212,13 @@ __device__ __forceinline__ int64_t sell_entry(int64_t off, int w, int u, int lan
 // inside the width with a column >= 0 enter a sum (the others gather the
 // row's own x): each row's sum has the same terms, order and rounding as the
 // CSR product.
-template <typename T, class Pre, class F>
+template <bool NT, typename V>
+__device__ __forceinline__ V sell_ld(const V *p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+
+template <bool NT, typename T, class Pre, class F>
 __device__ __forceinline__ void sell_rows(const CsrArgs<T> &A, const T *__restrict__ x, Pre &&pre,
                                           F &&f, T xs) {
 #pragma clang fp contract(off)
@@ -252,7 +258,7 @@ __device__ __forceinline__ void sell_rows(const CsrArgs<T> &A, const T *__restri
     header(0, off, w);
     int cc[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) cc[u] = A.sell_col[sell_entry(off, w, u, lane)];
+    for (int u = 0; u < U; ++u) cc[u] = sell_ld<NT>(&A.sell_col[sell_entry(off, w, u, lane)]);
     for (int t = 0; t < cnt; ++t) {
       const int64_t row = (g0 + WSX * t) * kWave + lane;
       const bool live = row < A.n;
@@ -264,7 +270,7 @@ __device__ __forceinline__ void sell_rows(const CsrArgs<T> &A, const T *__restri
       for (int u0 = 0; u0 < (sw > 0 ? sw : 1); u0 += U) {
         if (u0 > 0) {
 #pragma unroll
-          for (int u = 0; u < U; ++u) cc[u] = A.sell_col[sell_entry(so, sw, u0 + u, lane)];
+          for (int u = 0; u < U; ++u) cc[u] = sell_ld<NT>(&A.sell_col[sell_entry(so, sw, u0 + u, lane)]);
         }
         T xg[U], vv[U];
         bool ok[U];
@@ -272,13 +278,13 @@ __device__ __forceinline__ void sell_rows(const CsrArgs<T> &A, const T *__restri
         for (int u = 0; u < U; ++u) {
           ok[u] = (u0 + u < sw) && cc[u] >= 0;
           xg[u] = x[ok[u] ? cc[u] : (int)rowc];
-          vv[u] = A.sell_val[sell_entry(so, sw, u0 + u, lane)];
+          vv[u] = sell_ld<NT>(&A.sell_val[sell_entry(so, sw, u0 + u, lane)]);
         }
         if (u0 + U >= sw) {
           // last pass of this slice: start on the next slice's columns
           header(t + 1 < cnt ? t + 1 : t, off, w);
 #pragma unroll
-          for (int u = 0; u < U; ++u) cc[u] = A.sell_col[sell_entry(off, w, u, lane)];
+          for (int u = 0; u < U; ++u) cc[u] = sell_ld<NT>(&A.sell_col[sell_entry(off, w, u, lane)]);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -303,7 +309,11 @@ __device__ __forceinline__ void csr_rows(const CsrArgs<T> &A, const T *__restric
     block_chunk(A.n, logical_block(), gridDim.x, r0, r1);
     csr_rows_direct(A, x, r0, r1, pre, f, xs);
   } else if constexpr (VARIANT == CSR_SELL) {
-    sell_rows(A, x, pre, f, xs);
+    // a matrix larger than the memory-side cache streams its entries with the
+    // non-temporal hint (they are not reused before they would be evicted);
+    // a cache-resident one keeps them cached across the matrix powers
+    if (A.sell_xcd) sell_rows<true>(A, x, pre, f, xs);
+    else sell_rows<false>(A, x, pre, f, xs);
   } else {
     int64_t rb0, rb1;
     block_chunk(A.nrb, logical_block(), gridDim.x, rb0, rb1);
