@@ -814,11 +814,13 @@ static __global__ __attribute__((unused)) __launch_bounds__(kWG) void k_ir_add(i
 }
 
 // z = B^-1 v on its own (first column of the stand-alone matrix powers).
+// The row grid is capped, so each workgroup covers a chunk of rows.
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_prec(int64_t n, const T *__restrict__ v,
                                               T *__restrict__ z, Prec<T> pc) {
-  const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
-  if (i < n) z[i] = pc.apply(i, v[i]);
+  int64_t lo, hi;
+  block_chunk(n, logical_block(), gridDim.x, lo, hi);
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kWG) z[i] = pc.apply(i, v[i]);
 }
 
 }  // namespace ssp

@@ -370,3 +370,23 @@ def test_empty_rows_every_csr_form(H, monkeypatch, variant):
     assert np.array_equal(got, op.apply(x))
     assert np.all(got[::7] == 0.0)
     A.close()
+
+
+def test_mpk_beyond_the_row_grid_cap(H):
+    """The stand-alone matrix powers on more rows than the capped row grid
+    covers with one row per thread (2048 x 256 = 524288): every row of the
+    basis, the first column included, equals the oracle's."""
+    shape = (90, 80, 80)       # 576000 rows
+    k = np.exp(wl.gaussian_random_field(shape, 0.5, 0.1, 2))
+    csr = wl.stencil_csr("3d7_vark", shape, k=k)
+    op = oracle.Operator("csr", csr=csr)
+    n = len(csr[0]) - 1
+    r = wl.normal_rhs(n, 3)
+    A = H.matrix_csr(*[torch.from_numpy(a).cuda() for a in csr], flags=2)
+    try:
+        P = torch.full((6, n), np.nan, dtype=torch.float64, device="cuda")
+        H.mpk(A, dev(r), 3, P=P)
+        Pref, vmref = oracle.mpk_cvm(op, r, 3)
+        assert np.array_equal(host(P), Pref)
+    finally:
+        A.close()
