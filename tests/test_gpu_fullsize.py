@@ -5,12 +5,20 @@
   b ~ N(0, 1) with seed 0.  The oracle solves it in seconds, so the whole
   output is compared, not a sample: the matrix-powers basis bit for bit, the
   converged iterate to 1e-9 relative, the outer-iteration count within 2.
+* the benchmark's comparison rows on the same problem: the matrix-free
+  s-step form, PCG (Alg. 1) and PFCG (Alg. 2) to the same bars, and the
+  mixed-precision refinement checked with the oracle's own FP64 operator
+  (its x passes the FP64 residual test) and within cond(A) (2 rtol + 1e-13)
+  of the oracle's FP64 solution at the same rtol (both residuals are at most
+  rtol ||b||; closed-form condition number).
 * 256^3 (16.8M unknowns): the sliced-ELL matrix (1.4 GB) is larger than the
   256 MB memory-side cache, so its kernels take the XCD-interleaved schedule
   and the non-temporal matrix loads.  The basis is compared bit for bit and
   a fixed run of 10 outer iterations (the same iteration index on both
   sides) to 1e-9 relative, as the smaller fixed-iteration cases are.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -55,6 +63,55 @@ def test_bench_workload_128cubed(H):
         assert res.true_rel <= 1e-7
         m = min(res.outer, ref.outer)
         np.testing.assert_allclose(res.hist[:m + 1], ref.hist[:m + 1], rtol=1e-7)
+    finally:
+        A.close()
+
+
+def _kappa_3d7(N):
+    c1, cN = math.cos(math.pi / (N + 1)), math.cos(N * math.pi / (N + 1))
+    return (6 - 6 * cN) / (6 - 6 * c1)
+
+
+def _converged(res, ref, x, label):
+    assert ref.status == oracle.OK, label
+    assert res.status == 0 and abs(res.outer - ref.outer) <= 2, (label, res.outer, ref.outer)
+    assert _rel(host(x), ref.x) <= 1e-9, (label, _rel(host(x), ref.x))
+    assert res.true_rel <= 1e-7, label
+
+
+def test_bench_comparison_rows_128cubed(H):
+    N = 128
+    n = N ** 3
+    shape = (N, N, N)
+    csr = oracle.Operator("csr", csr=wl.stencil_csr("3d7", shape))
+    b = wl.normal_rhs(n, 0)
+    bd = dev(b)
+    # matrix-free s-step form
+    A = H.matrix_stencil("3d7", shape)
+    try:
+        ref = oracle.sstep(oracle.Operator("3d7", shape), b, S, rtol=1e-8, maxit=20000)
+        x = torch.zeros_like(bd)
+        _converged(H.solve(A, bd, x, s=S, rtol=1e-8, maxit=20000), ref, x, "stencil s-step")
+    finally:
+        A.close()
+    A = H.matrix_csr_from_stencil("3d7", shape)
+    try:
+        for method, fn in (("pcg", oracle.pcg), ("pfcg", oracle.pfcg)):
+            ref = fn(csr, b, rtol=1e-8, maxit=20000)
+            x = torch.zeros_like(bd)
+            res = H.solve(A, bd, x, method=method, rtol=1e-8, maxit=20000)
+            _converged(res, ref, x, method)
+        ref = oracle.sstep(csr, b, S, rtol=1e-8, maxit=20000)
+        x = torch.zeros_like(bd)
+        res = H.solve(A, bd, x, s=S, rtol=1e-8, maxit=20000, precision="mixed_ir")
+        assert res.status == 0 and res.true_rel <= 1e-8
+        xg = host(x)
+        r = b - csr.apply(xg)
+        assert np.linalg.norm(r) <= 1e-8 * np.linalg.norm(b) * 1.001
+        err = _rel(xg, ref.x)
+        print("128^3 mixed: refinements %d, distance to the FP64 solution %.2e"
+              % (len(res.hist) - 1, err), flush=True)
+        assert err <= _kappa_3d7(N) * (2e-8 + 1e-13)
     finally:
         A.close()
 
