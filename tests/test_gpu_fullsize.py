@@ -140,3 +140,41 @@ def test_sliced_ell_beyond_cache_256cubed(H, monkeypatch):
         assert np.allclose(res.hist, ref.hist, rtol=1e-8, atol=0)
     finally:
         A.close()
+
+
+def test_bench_batch_config(H):
+    """The benchmark's batch at its full size: 32 variable-coefficient 7-point
+    systems with seeded sides L ~ U{32..160} (up to 3.9M rows each), the
+    autotuned schedule, s = 4, rtol 1e-8.  Every returned x passes the FP64
+    residual test through the oracle's own operator, and the two smallest
+    systems are within the refinement bar of the oracle's FP64 solution."""
+    sides = [int(v) for v in wl.batch_sides(0, 32, 32, 160)]
+    mats, bs, ks = [], [], []
+    try:
+        for i, L in enumerate(sides):
+            shape = (L, L, L)
+            k = torch.exp(wl.gaussian_random_field_device(shape, 0.5, 0.1, 1000 + i))
+            mats.append(H.matrix_stencil("3d7_vark", shape, k=k))
+            bs.append(torch.from_numpy(wl.normal_rhs(L ** 3, 2000 + i)).cuda())
+            ks.append(k)
+        tune = H.autotune_batch(mats, bs, s=S)
+        xs = [torch.zeros_like(b) for b in bs]
+        rc, st, it, tr = H.solve_batch(mats, bs, xs, s=S, rtol=1e-8, maxit=20000, tune=tune)
+        assert rc == 0 and (st == 0).all(), st
+        assert (tr <= 1e-8).all(), tr
+        ops = {}
+        for i, L in enumerate(sides):
+            ops[i] = oracle.Operator("3d7_vark", (L, L, L), k=host(ks[i]))
+            b = host(bs[i])
+            rel = np.linalg.norm(b - ops[i].apply(host(xs[i]))) / np.linalg.norm(b)
+            assert rel <= 1e-8 * 1.001, (i, L, rel)
+            if i not in sorted(range(len(sides)), key=lambda j: sides[j])[:2]:
+                del ops[i]
+        for i, op in ops.items():
+            ref = oracle.sstep(op, host(bs[i]), S, rtol=1e-12, maxit=50000)
+            err = _rel(host(xs[i]), ref.x)
+            print("batch system %d (L=%d): err vs oracle %.2e" % (i, sides[i], err), flush=True)
+            assert err <= 1e-5
+    finally:
+        for M in mats:
+            M.close()
