@@ -178,3 +178,36 @@ def test_bench_batch_config(H):
     finally:
         for M in mats:
             M.close()
+
+
+def test_every_csr_form_variable_coefficient_128cubed(H, monkeypatch):
+    """A caller-supplied CSR matrix at 128^3 with a variable diagonal (k =
+    exp of a Gaussian random field, so the Jacobi scaling is stored, not a
+    constant), in each CSR kernel form (LDS-staged, row per thread, sliced
+    ELL): the product and the matrix-powers basis equal the oracle's bit for
+    bit."""
+    N = 128
+    shape = (N, N, N)
+    k = np.exp(wl.gaussian_random_field(shape, 0.5, 0.1, 21))
+    csr = wl.stencil_csr("3d7_vark", shape, k=k)
+    op = oracle.Operator("csr", csr=csr)
+    n = len(csr[0]) - 1
+    v = wl.normal_rhs(n, 22)
+    y_ref = op.apply(v)
+    P_ref, vm_ref = oracle.mpk_cvm(op, v, S)
+    dev_csr = [torch.from_numpy(a).cuda() for a in csr]
+    vd = dev(v)
+    for variant in ("0", "1", "2"):
+        monkeypatch.setenv("SSP_CSR_VARIANT", variant)
+        A = H.matrix_csr(*dev_csr, flags=2)
+        try:
+            assert A.csr_form == int(variant)
+            y = torch.full((n,), np.nan, dtype=torch.float64, device="cuda")
+            H.spmv(A, vd, y)
+            assert np.array_equal(host(y), y_ref), variant
+            P, vm = H.mpk(A, vd, S)
+            assert np.array_equal(host(P), P_ref), variant
+            assert np.allclose(vm, vm_ref, rtol=1e-12, atol=0), (variant, vm, vm_ref)
+            del P
+        finally:
+            A.close()
