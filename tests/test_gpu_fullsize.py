@@ -211,3 +211,28 @@ def test_every_csr_form_variable_coefficient_128cubed(H, monkeypatch):
             del P
         finally:
             A.close()
+
+
+def test_27point_matrix_free_256cubed(H):
+    """The 27-point operator at 256^3 in matrix-free form (the LDS-tiled
+    kernel, as in the benchmark's 27-point row): the basis bit for bit, and
+    3 fixed outer iterations to 1e-9 relative."""
+    N = 256
+    shape = (N, N, N)
+    op = oracle.Operator("3d27", shape)
+    b = wl.normal_rhs(N ** 3, 0)
+    bd = dev(b)
+    A = H.matrix_stencil("3d27", shape)
+    try:
+        P_ref, vm_ref = oracle.mpk_cvm(op, b, S)
+        P, vm = H.mpk(A, bd, S)
+        assert np.array_equal(host(P), P_ref)
+        assert np.allclose(vm, vm_ref, rtol=1e-12, atol=0), (vm, vm_ref)
+        del P, P_ref
+        ref = oracle.sstep(op, b, S, fixed_outer=3)
+        x = torch.zeros_like(bd)
+        res = H.solve(A, bd, x, s=S, fixed_outer=3)
+        assert res.outer == ref.outer == 3
+        assert _rel(host(x), ref.x) <= 1e-9, _rel(host(x), ref.x)
+    finally:
+        A.close()
