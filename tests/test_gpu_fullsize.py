@@ -15,7 +15,9 @@
   256 MB memory-side cache, so its kernels take the XCD-interleaved schedule
   and the non-temporal matrix loads.  The basis is compared bit for bit and
   a fixed run of 10 outer iterations (the same iteration index on both
-  sides) to 1e-9 relative, as the smaller fixed-iteration cases are.
+  sides) to 1e-9 relative, as the smaller fixed-iteration cases are; the
+  mixed-precision solve (FP32 sliced ELL on the same schedule) passes the
+  FP64 residual test through the oracle's operator.
 """
 import math
 
@@ -138,6 +140,14 @@ def test_sliced_ell_beyond_cache_256cubed(H, monkeypatch):
         assert res.outer == ref.outer == K
         assert _rel(host(x), ref.x) <= 1e-9, _rel(host(x), ref.x)
         assert np.allclose(res.hist, ref.hist, rtol=1e-8, atol=0)
+        # mixed precision: the FP32 copy of the sliced-ELL matrix takes the
+        # same schedule; its result passes the FP64 residual test through
+        # the oracle's own operator
+        x = torch.zeros_like(bd)
+        res = H.solve(A, bd, x, s=S, rtol=1e-8, maxit=20000, precision="mixed_ir")
+        assert res.status == 0 and res.true_rel <= 1e-8
+        r = b - op.apply(host(x))
+        assert np.linalg.norm(r) <= 1e-8 * np.linalg.norm(b) * 1.001
     finally:
         A.close()
 
