@@ -10,7 +10,8 @@
   mixed-precision refinement checked with the oracle's own FP64 operator
   (its x passes the FP64 residual test) and within cond(A) (2 rtol + 1e-13)
   of the oracle's FP64 solution at the same rtol (both residuals are at most
-  rtol ||b||; closed-form condition number).
+  rtol ||b||; closed-form condition number); s = 8 with residual
+  replacement by restart passes the FP64 residual test the same way.
 * 256^3 (16.8M unknowns): the sliced-ELL matrix (1.4 GB) is larger than the
   256 MB memory-side cache, so its kernels take the XCD-interleaved schedule
   and the non-temporal matrix loads.  The basis is compared bit for bit and
@@ -114,6 +115,16 @@ def test_bench_comparison_rows_128cubed(H):
         print("128^3 mixed: refinements %d, distance to the FP64 solution %.2e"
               % (len(res.hist) - 1, err), flush=True)
         assert err <= _kappa_3d7(N) * (2e-8 + 1e-13)
+        # s = 8 with residual replacement by restart: the monomial basis loses
+        # accuracy, the restart recovers it; the returned x passes the FP64
+        # residual test through the oracle's operator
+        x = torch.zeros_like(bd)
+        res = H.solve(A, bd, x, s=8, rtol=1e-8, maxit=20000, restarts=2)
+        print("128^3 s=8: restarts %d, true residual %.2e" % (res.restarts, res.true_rel),
+              flush=True)
+        assert res.status == 0 and res.true_rel <= 1e-8
+        r = b - csr.apply(host(x))
+        assert np.linalg.norm(r) <= 1e-8 * np.linalg.norm(b) * 1.001
     finally:
         A.close()
 
