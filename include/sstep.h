@@ -166,13 +166,13 @@ int ssp_matrix_info(const ssp_matrix *A, int64_t *n, int64_t *nnz);
 
 /* Device pointers of a CSR matrix (borrowed, copied or library-built);
  * SSP_EINVAL for a matrix-free operator. */
+int ssp_matrix_csr_arrays(const ssp_matrix *A, const int32_t **rowptr,
+                          const int32_t **colind, const double **val);
+
 /* The CSR kernel form chosen for A at creation by timing (0 = LDS-staged row
  * blocks, 1 = one row per thread, 2 = sliced ELL copy, slices of 64 rows);
  * -1 for matrix-free operators. */
 int ssp_matrix_csr_form(const ssp_matrix *A, int *form);
-
-int ssp_matrix_csr_arrays(const ssp_matrix *A, const int32_t **rowptr,
-                          const int32_t **colind, const double **val);
 
 int ssp_matrix_destroy(ssp_matrix *A);
 

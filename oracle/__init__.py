@@ -250,10 +250,10 @@ def _restarted(run, x0, rtol, maxit, s, restarts):
 
 
 def pcg(op: Operator, b, x0=None, rtol=1e-8, maxit=10000, prec=PREC_JACOBI, restarts=0):
-    """Alg. 1; with restarts > 0, residual replacement by restart (_restarted)."""
+    """Alg. 1 on the oracle operator; returns a Result with x and history.
+    restarts > 0: residual replacement by restart (_restarted)."""
     if restarts > 0:
         return _restarted(lambda x, m: pcg(op, b, x, rtol, m, prec), x0, rtol, maxit, 1, restarts)
-    """Alg. 1 on the oracle operator; returns a Result with x and history."""
     b = np.ascontiguousarray(b, dtype=np.float64)
     x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
     hist = np.zeros(maxit + 2)

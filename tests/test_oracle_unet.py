@@ -206,6 +206,37 @@ def test_adam_first_step_is_signed_lr():
     np.testing.assert_allclose(P["a"], P0 - 0.01 * np.sign(G["a"]), rtol=0, atol=1e-15)
 
 
+def test_adam_constant_gradient_steps_are_signed_lr():
+    # with the same gradient g at steps 1..t from zero moments,
+    # m_t = (1 - b1^t) g and v_t = (1 - b2^t) g^2, so the bias-corrected
+    # moments are g and g^2 at EVERY step and each step moves by lr sign(g)
+    # (eps = 0); a bias correction of 1 - b1*t instead of 1 - b1^t fails at t = 2
+    g = np.random.default_rng(8)
+    G = {"a": g.standard_normal(16)}
+    P = {"a": g.standard_normal(16)}
+    M = {"a": np.zeros(16)}
+    V = {"a": np.zeros(16)}
+    for t in (1, 2, 3):
+        P0 = P["a"].copy()
+        U.adam(P, G, M, V, t, lr=0.01, eps=0.0)
+        np.testing.assert_allclose(P["a"] - P0, -0.01 * np.sign(G["a"]), rtol=1e-12, atol=0)
+
+
+def test_adam_two_steps_by_hand():
+    # scalar gradients 1 then -2, b1 = 0.9, b2 = 0.999, lr = 1, eps = 0:
+    # m2 = 0.9*0.1 - 0.2 = -0.11, v2 = 0.999*0.001 + 0.004 = 0.004999,
+    # m_hat = -0.11/0.19 = -11/19, v_hat = 0.004999/0.001999 = 4999/1999,
+    # second step = -m_hat/sqrt(v_hat) = (11/19) sqrt(1999/4999)
+    P = {"a": np.zeros(1)}
+    M = {"a": np.zeros(1)}
+    V = {"a": np.zeros(1)}
+    U.adam(P, {"a": np.array([1.0])}, M, V, 1, lr=1.0, eps=0.0)
+    np.testing.assert_allclose(P["a"], [-1.0], rtol=1e-15)
+    U.adam(P, {"a": np.array([-2.0])}, M, V, 2, lr=1.0, eps=0.0)
+    step2 = (11.0 / 19.0) * (1999.0 / 4999.0) ** 0.5
+    np.testing.assert_allclose(P["a"], [-1.0 + step2], rtol=1e-13)
+
+
 def test_param_count():
     P = U.init_params(0)
     n = sum(v.size for v in P.values())
