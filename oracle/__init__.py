@@ -7,8 +7,11 @@ no fast-math, no FMA contraction); this module only compiles and binds it.
 ``exact.py`` holds a rational-arithmetic version for tiny problems.
 
 Functions follow the paper's algorithms:
-  pcg    -- Alg. 1 (PCG-HS)
-  sstep  -- Alg. 3 with Alg. 4 (pMPK), Alg. 5 (cvm) and Alg. 6 (SW)
+  pcg         -- Alg. 1 (PCG-HS)
+  pfcg        -- Alg. 2 (PFCG)
+  sstep       -- Alg. 3 with Alg. 4 (pMPK), Alg. 5 (cvm) and Alg. 6 (SW)
+  sstep_cheb  -- Alg. 3 on a Chebyshev basis with an explicit block Gram
+                 product (the stabilised bases of the related work, Sec. IV)
 """
 from __future__ import annotations
 
@@ -92,6 +95,16 @@ def lib():
             _lib.orc_mpk_cvm.argtypes = [C.POINTER(_Op), C.c_int, C.c_void_p, C.c_int, C.c_void_p,
                                          C.c_void_p]
             _lib.orc_sw.argtypes = [C.c_int] + [C.c_void_p] * 6
+            _lib.orc_sstep_cheb.restype = C.c_int
+            _lib.orc_sstep_cheb.argtypes = [C.POINTER(_Op), C.c_int, C.c_void_p, C.c_void_p,
+                                            C.c_int, C.c_double, C.c_double, C.c_double,
+                                            C.c_int, C.c_int, C.POINTER(_Res),
+                                            C.POINTER(_Trace)]
+            _lib.orc_cheb_basis.restype = C.c_int
+            _lib.orc_cheb_basis.argtypes = [C.POINTER(_Op), C.c_int, C.c_void_p, C.c_int,
+                                            C.c_double, C.c_double, C.c_void_p]
+            _lib.orc_max_diag.restype = C.c_double
+            _lib.orc_max_diag.argtypes = [C.POINTER(_Op)]
         return _lib
 
 
@@ -310,4 +323,55 @@ def sstep(op: Operator, b, s, x0=None, rtol=1e-8, maxit=10000, prec=PREC_JACOBI,
         ln = tr.len
         trace = {k: v[:ln] for k, v in trace.items()}
         trace = {"trace": trace}
+    return _result(res, hist, x, trace)
+
+
+def basis_interval(op: Operator, prec=PREC_JACOBI):
+    """Default interval [lo, hi] enclosing the spectrum of K = B^-1 A for the
+    Chebyshev basis: [0, 2] with the Jacobi preconditioner, [0, 2 max a_ii]
+    without one (Gershgorin, for weakly diagonally dominant SPD matrices)."""
+    if prec == PREC_JACOBI:
+        return 0.0, 2.0
+    return 0.0, 2.0 * lib().orc_max_diag(C.byref(op._op))
+
+
+def cheb_basis(op: Operator, r, s, lo, hi, prec=PREC_JACOBI):
+    """The Chebyshev basis block of one outer iteration: (2s, n) array
+    [z_1 .. z_s, A z_1 .. A z_s] for z_1 = B^-1 r."""
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    P = np.zeros((2 * s, op.n))
+    rc = lib().orc_cheb_basis(C.byref(op._op), prec, _ptr(r), s, lo, hi, _ptr(P))
+    if rc:
+        raise ValueError("orc_cheb_basis: %d" % rc)
+    return P
+
+
+def sstep_cheb(op: Operator, b, s, x0=None, rtol=1e-8, maxit=10000, prec=PREC_JACOBI,
+               interval=None, fixed_outer=0, trace_cap=0, trace_P=False, restarts=0):
+    """Alg. 3 on a Chebyshev basis with the block Gram product taken directly
+    (``orc_sstep_cheb``).  ``interval`` = (lo, hi) encloses the spectrum of
+    B^-1 A (default: ``basis_interval``).  The trace's ``vm`` holds m(1..s)
+    then the diagonal of Z^T A Z.  Other arguments as for ``sstep``."""
+    lo, hi = basis_interval(op, prec) if interval is None else interval
+    if restarts > 0:
+        return _restarted(lambda x, m: sstep_cheb(op, b, s, x, rtol, m, prec, (lo, hi)), x0,
+                          rtol, maxit, s, restarts)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+    outer_cap = fixed_outer if fixed_outer > 0 else (maxit + max(s, 1) - 1) // max(s, 1)
+    hist = np.zeros(outer_cap + 2)
+    res = _Res(hist=_ptr(hist), hist_cap=hist.size)
+    tr = trace = None
+    if trace_cap > 0:
+        trace = dict(vm=np.zeros((trace_cap, 2 * s)), alpha=np.zeros((trace_cap, s)),
+                     beta=np.zeros((trace_cap, s, s)), W=np.zeros((trace_cap, s, s)))
+        if trace_P:
+            trace["P"] = np.zeros((trace_cap, 2 * s, op.n))
+        tr = _Trace(cap=trace_cap, len=0, vm=_ptr(trace["vm"]), alpha=_ptr(trace["alpha"]),
+                    beta=_ptr(trace["beta"]), W=_ptr(trace["W"]),
+                    P=_ptr(trace["P"]) if trace_P else None)
+    lib().orc_sstep_cheb(C.byref(op._op), prec, _ptr(b), _ptr(x), s, lo, hi, rtol, maxit,
+                         fixed_outer, C.byref(res), C.byref(tr) if tr is not None else None)
+    if trace is not None:
+        trace = {"trace": {k: v[:tr.len] for k, v in trace.items()}}
     return _result(res, hist, x, trace)

@@ -170,3 +170,72 @@ def sstep(A, b, bdiag, s, outer, b1_printed_bound=False):
         if all(v == 0 for v in r):
             break
     return dict(x=xs, vm=vms, alpha=alphas, beta=betas, W=Ws)
+
+
+def sstep_cheb(A, b, bdiag, s, outer, lo, hi, ap_conj_sign=1):
+    """Alg. 3 on a Chebyshev basis with the block Gram product taken directly
+    (the stabilised-basis variant; see ``orc_sstep_cheb``), exactly, for
+    ``outer`` outer iterations.  [lo, hi] (Fractions) encloses the spectrum of
+    K = B^-1 A: z_1 = B^-1 r, z_2 = (K - c) z_1 / h,
+    z_{j+1} = 2 (K - c) z_j / h - z_{j-1}, c = (hi + lo)/2, h = (hi - lo)/2.
+    With C = P_{i-1}^T A Z_i: W_{i-1} beta = -C, W_i = Z^T A Z + C^T beta,
+    W_i alpha = Z^T r.  Returns a dict with the iterates and, per iteration,
+    alpha, beta, W and the block [P_i | A P_i].
+
+    ``ap_conj_sign`` = -1 flips the sign of the conjugation coefficients
+    (tests use it to show that the pins catch such a slip)."""
+    n = len(b)
+    lo, hi = Fr(lo), Fr(hi)
+    c, h = (hi + lo) / 2, (hi - lo) / 2
+    x = [Fr(0)] * n
+    r = list(map(Fr, b))
+    Pold = None
+    W_prev = None
+    xs, alphas, betas, Ws, blocks = [list(x)], [], [], [], []
+    for k in range(outer):
+        Z = [_binv(bdiag, r)]
+        AZ = []
+        for j in range(s):
+            AZ.append(_mv(A, Z[j]))
+            if j + 1 == s:
+                break
+            Kz = _binv(bdiag, AZ[j])
+            u = [t - c * zz for t, zz in zip(Kz, Z[j])]
+            if j == 0:
+                Z.append([v / h for v in u])
+            else:
+                Z.append([2 * v / h - zm for v, zm in zip(u, Z[j - 1])])
+        ZAZ = [[_dot(Z[a], AZ[q]) for q in range(s)] for a in range(s)]
+        m = [_dot(Z[a], r) for a in range(s)]
+        if k == 0:
+            beta = [[Fr(0)] * s for _ in range(s)]
+            W = ZAZ
+        else:
+            Cm = [[_dot(Pold[s + l], Z[j]) for j in range(s)] for l in range(s)]
+            bcols = [_solve(W_prev, [-ap_conj_sign * Cm[i][j] for i in range(s)])
+                     for j in range(s)]
+            beta = [[bcols[j][i] for j in range(s)] for i in range(s)]
+            W = [[ZAZ[i][j] + sum((Cm[l][i] * beta[l][j] for l in range(s)), Fr(0))
+                  for j in range(s)] for i in range(s)]
+        alpha = _solve(W, m)
+        cols = [list(v) for v in Z] + [list(v) for v in AZ]
+        if Pold is not None:
+            for j in range(s):
+                for l in range(s):
+                    if beta[l][j] != 0:
+                        cols[j] = [cc + po * beta[l][j] for cc, po in zip(cols[j], Pold[l])]
+                        cols[s + j] = [cc + po * beta[l][j]
+                                       for cc, po in zip(cols[s + j], Pold[s + l])]
+        for j in range(s):
+            x = [xi + cj * alpha[j] for xi, cj in zip(x, cols[j])]
+            r = [ri - cj * alpha[j] for ri, cj in zip(r, cols[s + j])]
+        Pold = cols
+        W_prev = W
+        xs.append(list(x))
+        alphas.append(alpha)
+        betas.append(beta)
+        Ws.append(W)
+        blocks.append(cols)
+        if all(v == 0 for v in r):
+            break
+    return dict(x=xs, alpha=alphas, beta=betas, W=Ws, P=blocks)

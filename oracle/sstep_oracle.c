@@ -637,6 +637,38 @@ static int sw(int s, const double *vm, const double *alpha_prev, const double *L
 /* Alg. 3: preconditioned s-step CG                                          */
 /* ------------------------------------------------------------------------ */
 
+/* The four update lines of Alg. 3, in their order:
+ *   P(:,1:s) += Pold(:,1:s) beta;   x += P(:,1:s) alpha;
+ *   P(:,s+1:2s) += Pold(:,s+1:2s) beta;   r -= P(:,s+1:2s) alpha
+ * (the Pold terms are skipped at k = 0, where Pold = 0). */
+static void block_update(int64_t n, int s, int k, const double *beta, const double *alpha,
+                         double *Pcur, const double *Pold, double *x, double *r) {
+  for (int half = 0; half < 2; ++half) {
+    double *Pc = Pcur + (int64_t)half * s * n;
+    const double *Po = Pold + (int64_t)half * s * n;
+    if (k > 0) {
+#pragma omp parallel for schedule(static)
+      for (int64_t i = 0; i < n; ++i) {
+        double old[ORC_SMAX];
+        for (int l = 0; l < s; ++l) old[l] = Po[(int64_t)l * n + i];
+        for (int j = 0; j < s; ++j) {
+          double acc = Pc[(int64_t)j * n + i];
+          for (int l = 0; l < s; ++l) acc += old[l] * beta[l * s + j];
+          Pc[(int64_t)j * n + i] = acc;
+        }
+      }
+    }
+    double *tgt = half == 0 ? x : r;
+    double sgn = half == 0 ? 1.0 : -1.0;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+      double acc = 0.0;
+      for (int j = 0; j < s; ++j) acc += Pc[(int64_t)j * n + i] * alpha[j];
+      tgt[i] += sgn * acc;
+    }
+  }
+}
+
 /* fixed_outer > 0 runs exactly that many outer iterations (no stopping test)
  * unless a breakdown occurs; the final status then says whether the residual
  * test holds at the end.  tr may be NULL. */
@@ -704,32 +736,7 @@ int orc_sstep(const orc_op *A, int prec, const double *b, double *x, int s,
       bad = sw(s, vm, alpha_prev, Lprev, beta, W, L, alpha);
     }
     if (bad) { status = ORC_BREAKDOWN; break; }
-    /* P(:,1:s) += Pold(:,1:s) beta; x += P(:,1:s) alpha;
-       P(:,s+1:2s) += Pold(:,s+1:2s) beta; r -= P(:,s+1:2s) alpha */
-    for (int half = 0; half < 2; ++half) {
-      double *Pc = Pcur + (int64_t)half * s * n;
-      const double *Po = Pold + (int64_t)half * s * n;
-      if (k > 0) {
-#pragma omp parallel for schedule(static)
-        for (int64_t i = 0; i < n; ++i) {
-          double old[ORC_SMAX];
-          for (int l = 0; l < s; ++l) old[l] = Po[(int64_t)l * n + i];
-          for (int j = 0; j < s; ++j) {
-            double acc = Pc[(int64_t)j * n + i];
-            for (int l = 0; l < s; ++l) acc += old[l] * beta[l * s + j];
-            Pc[(int64_t)j * n + i] = acc;
-          }
-        }
-      }
-      double *tgt = half == 0 ? x : r;
-      double sgn = half == 0 ? 1.0 : -1.0;
-#pragma omp parallel for schedule(static)
-      for (int64_t i = 0; i < n; ++i) {
-        double acc = 0.0;
-        for (int j = 0; j < s; ++j) acc += Pc[(int64_t)j * n + i] * alpha[j];
-        tgt[i] += sgn * acc;
-      }
-    }
+    block_update(n, s, k, beta, alpha, Pcur, Pold, x, r);
     if (tr && k < tr->cap) {
       memcpy(tr->vm + (size_t)k * 2 * s, vm, sizeof(double) * 2 * s);
       memcpy(tr->alpha + (size_t)k * s, alpha, sizeof(double) * s);
@@ -755,6 +762,215 @@ int orc_sstep(const orc_op *A, int prec, const double *b, double *x, int s,
   res->status = status;
   free(r); free(tmp); free(dinv); free(P1); free(P2);
   return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* s-step PCG on a Chebyshev basis with an explicit block Gram product       */
+/* ------------------------------------------------------------------------ */
+/*
+ * The stabilised-basis variant (related work, Sec. IV: Newton and Chebyshev
+ * bases; Sec. II-A: the monomial basis loses independence as s grows).  Alg. 3
+ * is kept: directions P_i = Z_i + P_{i-1} beta_{i-1} with beta chosen so that
+ * P_i is A-conjugate to P_{i-1}, W_i = P_i^T A P_i, alpha_i = W_i^{-1} Z_i^T r_i,
+ * and the same four update lines.  Only the basis and the way the s x s
+ * matrices are obtained change:
+ *
+ *   basis (K = B^{-1} A, interval [lo, hi] enclosing the spectrum of K,
+ *   c = (hi + lo)/2, h = (hi - lo)/2, T_j the Chebyshev polynomials):
+ *     z_1 = B^{-1} r,   z_{j+1} = T_j((K - c I)/h) z_1, i.e.
+ *     z_2 = (K z_1 - c z_1)/h,   z_{j+1} = 2 (K z_j - c z_j)/h - z_{j-1};
+ *     AZ(:,j) = A z_j, and K z_j = B^{-1} AZ(:,j) reuses that product.
+ *
+ *   Gram (the moments of Alg. 5 do not describe a non-monomial basis, so the
+ *   inner products are taken directly):
+ *     ZAZ(a,b) = z_a^T AZ(:,b),  ZAP(a,l) = z_a^T AP_{i-1}(:,l),  m(a) = z_a^T r.
+ *
+ *   s x s part (k > 0), with C = P_{i-1}^T A Z_i, i.e. C(l,j) = ZAP(j,l):
+ *     W_{i-1} beta = -C          (A-conjugacy of P_i and P_{i-1}),
+ *     W_i = ZAZ + C^T beta       (= P_i^T A P_i, using W_{i-1} beta = -C),
+ *     W_i alpha = m              (eq. (3); P_{i-1}^T r_i = 0).
+ *   At k = 0: W = ZAZ, beta = 0.  Cholesky of the lower triangle as in sw().
+ *
+ * Per element, in this order and rounding (contract off):
+ *   t = dinv_i * AZ(i,j)  (t = AZ(i,j) without preconditioner),
+ *   u = t - c * z_j(i),   z_{j+1}(i) = g * u (j = 1) or g2 * u - z_{j-1}(i),
+ * with g = 1/h and g2 = 2 g.
+ */
+static void cheb_basis(const orc_op *A, int prec, const double *dinv, const double *r, int s,
+                       double c, double g, double g2, double *P) {
+  int64_t n = A->n;
+  prec_apply(prec, n, dinv, r, P);                       /* z_1 = B^{-1} r */
+  for (int j = 1; j <= s; ++j) {
+    const double *zj = P + (int64_t)(j - 1) * n;
+    double *az = P + (int64_t)(s + j - 1) * n;
+    orc_apply(A, zj, az);                                /* AZ(:,j) = A z_j */
+    if (j == s) break;
+    double *zn = P + (int64_t)j * n;
+    const double *zm = j >= 2 ? P + (int64_t)(j - 2) * n : NULL;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+      double t = (prec == ORC_PREC_JACOBI) ? dinv[i] * az[i] : az[i];   /* (K z_j)(i) */
+      double cz = c * zj[i];
+      double u = t - cz;
+      if (j == 1) {
+        zn[i] = g * u;
+      } else {
+        double v = g2 * u;
+        zn[i] = v - zm[i];
+      }
+    }
+  }
+}
+
+int orc_sstep_cheb(const orc_op *A, int prec, const double *b, double *x, int s, double lo,
+                   double hi, double rtol, int maxit, int fixed_outer, orc_result *res,
+                   orc_trace *tr) {
+  res->status = ORC_EINVAL;
+  res->outer = res->cg_equiv = 0;
+  res->hist_len = 0;
+  res->true_rel = NAN;
+  if (tr) tr->len = 0;
+  if (!op_check(A) || s < 1 || s > ORC_SMAX || maxit < 0 || (A->n > 0 && s > A->n) ||
+      !(hi > lo))
+    return ORC_EINVAL;
+  int64_t n = A->n;
+  double *r = malloc((size_t)n * sizeof(double));
+  double *tmp = malloc((size_t)n * sizeof(double));
+  double *dinv = malloc((size_t)n * sizeof(double));
+  double *P1 = calloc((size_t)n * 2 * s, sizeof(double));
+  double *P2 = calloc((size_t)n * 2 * s, sizeof(double));
+  if (!r || !tmp || !dinv || !P1 || !P2) {
+    free(r); free(tmp); free(dinv); free(P1); free(P2);
+    res->status = ORC_ENOMEM;
+    return ORC_ENOMEM;
+  }
+  op_diag(A, dinv);
+  for (int64_t i = 0; i < n; ++i) dinv[i] = 1.0 / dinv[i];
+  const double c = 0.5 * (hi + lo), h = 0.5 * (hi - lo);
+  const double g = 1.0 / h, g2 = 2.0 * g;
+
+  double bn = nrm2(n, b);
+  int status = ORC_NOT_CONVERGED;
+  if (bn == 0.0) {
+    memset(x, 0, (size_t)n * sizeof(double));
+    hist_push(res, 0.0);
+    res->status = ORC_OK;
+    res->true_rel = 0.0;
+    free(r); free(tmp); free(dinv); free(P1); free(P2);
+    return ORC_OK;
+  }
+  residual(A, b, x, r, tmp);                 /* r = b - A x0 */
+  double rn = nrm2(n, r);
+  hist_push(res, rn / bn);
+  int outer_max = fixed_outer > 0 ? fixed_outer : (maxit + s - 1) / s;
+  if (fixed_outer <= 0 && rn <= rtol * bn) { status = ORC_OK; outer_max = 0; }
+
+  double m[ORC_SMAX], alpha[ORC_SMAX];
+  double ZAZ[ORC_SMAX * ORC_SMAX], ZAP[ORC_SMAX * ORC_SMAX], C[ORC_SMAX * ORC_SMAX];
+  double beta[ORC_SMAX * ORC_SMAX], W[ORC_SMAX * ORC_SMAX];
+  double L[ORC_SMAX * ORC_SMAX], Lprev[ORC_SMAX * ORC_SMAX];
+  double *Pcur = P2, *Pold = P1;             /* k even writes P2, k odd P1 */
+  for (int k = 0; k < outer_max; ++k) {
+    cheb_basis(A, prec, dinv, r, s, c, g, g2, Pcur);
+    /* block Gram: Z^T [AZ | AP_{i-1} | r] */
+    for (int a = 0; a < s; ++a) {
+      const double *za = Pcur + (int64_t)a * n;
+      m[a] = orc_dot(n, za, r);
+      for (int q = 0; q < s; ++q) {
+        ZAZ[a * s + q] = orc_dot(n, za, Pcur + (int64_t)(s + q) * n);
+        ZAP[a * s + q] = k > 0 ? orc_dot(n, za, Pold + (int64_t)(s + q) * n) : 0.0;
+      }
+    }
+    int bad = 0;
+    if (k == 0) {
+      for (int i = 0; i < s * s; ++i) { W[i] = ZAZ[i]; beta[i] = 0.0; }
+    } else {
+      /* C(l,j) = AP_{i-1}(:,l)^T z_j;  W_{i-1} beta = -C, column by column */
+      for (int l = 0; l < s; ++l)
+        for (int j = 0; j < s; ++j) C[l * s + j] = ZAP[j * s + l];
+      for (int j = 0; j < s; ++j) {
+        double col[ORC_SMAX];
+        for (int i = 0; i < s; ++i) col[i] = -C[i * s + j];
+        chol_solve(s, Lprev, col);
+        for (int i = 0; i < s; ++i) {
+          beta[i * s + j] = col[i];
+          if (!isfinite(col[i])) bad = 1;
+        }
+      }
+      /* W = ZAZ + C^T beta */
+      for (int i = 0; i < s; ++i)
+        for (int j = 0; j < s; ++j) {
+          double acc = 0.0;
+          for (int l = 0; l < s; ++l) acc += C[l * s + i] * beta[l * s + j];
+          W[i * s + j] = ZAZ[i * s + j] + acc;
+        }
+    }
+    if (!bad) bad = chol(s, W, L);
+    if (!bad) {
+      for (int i = 0; i < s; ++i) alpha[i] = m[i];   /* W alpha = m */
+      chol_solve(s, L, alpha);
+      for (int i = 0; i < s; ++i) if (!isfinite(alpha[i])) bad = 1;
+    }
+    if (bad) { status = ORC_BREAKDOWN; break; }
+    block_update(n, s, k, beta, alpha, Pcur, Pold, x, r);
+    if (tr && k < tr->cap) {
+      /* vm holds m(1..s) followed by the diagonal ZAZ(a,a) */
+      for (int a = 0; a < s; ++a) {
+        tr->vm[(size_t)k * 2 * s + a] = m[a];
+        tr->vm[(size_t)k * 2 * s + s + a] = ZAZ[a * s + a];
+      }
+      memcpy(tr->alpha + (size_t)k * s, alpha, sizeof(double) * s);
+      memcpy(tr->beta + (size_t)k * s * s, beta, sizeof(double) * s * s);
+      memcpy(tr->W + (size_t)k * s * s, W, sizeof(double) * s * s);
+      if (tr->P) memcpy(tr->P + (size_t)k * 2 * s * n, Pcur, sizeof(double) * 2 * s * n);
+      tr->len = k + 1;
+    }
+    memcpy(Lprev, L, sizeof(L));
+    double *t = Pcur; Pcur = Pold; Pold = t;
+    res->outer = k + 1;
+    rn = nrm2(n, r);
+    hist_push(res, rn / bn);
+    if (fixed_outer <= 0 && rn <= rtol * bn) { status = ORC_OK; break; }
+  }
+  if (fixed_outer > 0 && status != ORC_BREAKDOWN)
+    status = (rn <= rtol * bn) ? ORC_OK : ORC_NOT_CONVERGED;
+  residual(A, b, x, r, tmp);
+  res->true_rel = nrm2(n, r) / bn;
+  res->cg_equiv = res->outer * s;
+  res->status = status;
+  free(r); free(tmp); free(dinv); free(P1); free(P2);
+  return status;
+}
+
+/* The Chebyshev basis of one outer iteration on its own (tests): P is n x 2s
+ * column-major, [Z | AZ] for z_1 = B^{-1} r. */
+int orc_cheb_basis(const orc_op *A, int prec, const double *r, int s, double lo, double hi,
+                   double *P) {
+  if (!op_check(A) || s < 1 || s > ORC_SMAX || !(hi > lo)) return ORC_EINVAL;
+  double *dinv = malloc((size_t)A->n * sizeof(double));
+  if (!dinv) return ORC_ENOMEM;
+  op_diag(A, dinv);
+  for (int64_t i = 0; i < A->n; ++i) dinv[i] = 1.0 / dinv[i];
+  const double c = 0.5 * (hi + lo), h = 0.5 * (hi - lo);
+  const double g = 1.0 / h;
+  cheb_basis(A, prec, dinv, r, s, c, g, 2.0 * g, P);
+  free(dinv);
+  return ORC_OK;
+}
+
+/* Largest diagonal entry of the operator (exact: a maximum of stored or
+ * computed diagonal values).  The default basis interval without a
+ * preconditioner is [0, 2 max_i a_ii], which encloses the spectrum of a
+ * weakly diagonally dominant SPD matrix (Gershgorin); with the Jacobi
+ * preconditioner it is [0, 2]. */
+double orc_max_diag(const orc_op *A) {
+  double *d = malloc((size_t)A->n * sizeof(double));
+  if (!d) return NAN;
+  op_diag(A, d);
+  double mx = -INFINITY;
+  for (int64_t i = 0; i < A->n; ++i) if (d[i] > mx) mx = d[i];
+  free(d);
+  return mx;
 }
 
 /* Dense Cholesky solve of W y = c for a caller's s x s SPD matrix (test use:
