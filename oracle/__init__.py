@@ -105,6 +105,8 @@ def lib():
                                             C.c_double, C.c_double, C.c_void_p]
             _lib.orc_max_diag.restype = C.c_double
             _lib.orc_max_diag.argtypes = [C.POINTER(_Op)]
+            _lib.orc_set_threads.restype = C.c_int
+            _lib.orc_set_threads.argtypes = [C.c_int]
         return _lib
 
 
@@ -375,3 +377,9 @@ def sstep_cheb(op: Operator, b, s, x0=None, rtol=1e-8, maxit=10000, prec=PREC_JA
     if trace is not None:
         trace = {"trace": {k: v[:tr.len] for k, v in trace.items()}}
     return _result(res, hist, x, trace)
+
+
+def set_threads(n: int = 0) -> int:
+    """Threads of the oracle's OpenMP loops from now on (n <= 0: unchanged);
+    returns the number in use."""
+    return lib().orc_set_threads(int(n))

@@ -1008,3 +1008,17 @@ int orc_sw(int s, const double *vm, const double *alpha_prev, const double *Wpre
 }
 
 int orc_smax(void) { return ORC_SMAX; }
+
+/* Threads of the oracle's parallel loops from now on (timing runs). */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+int orc_set_threads(int nthreads) {
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+  return omp_get_max_threads();
+#else
+  (void)nthreads;
+  return 1;
+#endif
+}
