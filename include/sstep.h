@@ -192,6 +192,20 @@ int ssp_spmv(ssp_handle *h, const ssp_matrix *A, const double *x, double *y);
 int ssp_mpk(ssp_handle *h, const ssp_matrix *A, const double *r, int s, double *P,
             int64_t ld, double *vm);
 
+/* ssp_mpk without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, kernels and results (bit for bit) as ssp_mpk.
+ * Its control block and per-workgroup partial sums live in one static
+ * device array per GPU of 7 KB + 512 KiB (room for 2048 workgroups x 2s
+ * partial sums at s <= SSP_SMAX; a call needing more is rejected with
+ * SSP_EINVAL), set up once per device by ssp_create and held until the
+ * process ends.  Every call on a GPU shares that array: calls that overlap
+ * on one GPU (other streams, other handles, other host threads) race and
+ * must be serialised by the caller.  The caller still owns r, P and vm;
+ * the matrix must have been created beforehand (creation allocates). */
+int ssp_mpk_noalloc(ssp_handle *h, const ssp_matrix *A, const double *r, int s, double *P,
+                    int64_t ld, double *vm);
+
 /* ---- solve ------------------------------------------------------------------ */
 
 /* Solves A x = b.  b (n) and x (n, in: x0, out: solution) are DEVICE pointers

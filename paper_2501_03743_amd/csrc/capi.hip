@@ -2,6 +2,8 @@
 // kernels.  Host code only orders launches on the handle's stream, polls the
 // device status word every few outer iterations and copies results back;
 // every arithmetic step of a solve runs in the kernels.
+#include <mutex>
+
 #include "engine.hpp"
 #include "setup_kernels.hpp"
 
@@ -79,6 +81,36 @@ int ensure_fp32(ssp_handle *h, ssp_matrix *A) {
 }  // namespace ssp
 
 namespace {
+
+// Scratch of the allocation-free entry point (ssp_mpk_noalloc): the control
+// block of the call, then the per-workgroup partial sums of the moments
+// (at most kGridMax workgroups x 2 kSMax values).  One copy per GPU, held
+// until the process ends.  Host code never names the array in a launch or a
+// copy: it uses the device address that hipGetSymbolAddress returned for the
+// current device at ssp_create (scratch_addr below).
+constexpr size_t kScratchState = (sizeof(DevState) + 255) / 256 * 256;
+constexpr size_t kScratchPartials = (size_t)kGridMax * 2 * kSMax;   // doubles
+constexpr size_t kScratchBytes = kScratchState + kScratchPartials * sizeof(double);
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void *scratch_addr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (the current device), looked up
+// once per device.
+int scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return SSP_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (scratch_addr[device]) return SSP_OK;
+  void *p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+    (void)hipGetLastError();
+    return SSP_EHIP;
+  }
+  scratch_addr[device] = p;
+  return SSP_OK;
+}
 
 void hfree(void *&p) {
   if (p) (void)hipFree(p);
@@ -179,8 +211,10 @@ int ensure_workspace32(ssp_handle *h, int64_t n, int s) {
   return SSP_OK;
 }
 
-// Writes the header of the device control block (status, options).
-int state_init(ssp_handle *h, int s, int outer_max, int fixed, double rtol, int hist_cap) {
+// Writes the header of the device control block (status, options): the
+// handle's, or `dst` when given.
+int state_init(ssp_handle *h, int s, int outer_max, int fixed, double rtol, int hist_cap,
+               DevState *dst = nullptr) {
   DevState *c = h->h_init;
   HIPCHK(h, hipStreamSynchronize(h->stream));  // staging buffer reuse
   memset(c, 0, offsetof(DevState, vm));
@@ -191,13 +225,15 @@ int state_init(ssp_handle *h, int s, int outer_max, int fixed, double rtol, int 
   c->s = s;
   c->hist_cap = hist_cap;
   c->rtol = rtol;
-  HIPCHK(h, hipMemcpyAsync(h->st, c, offsetof(DevState, vm), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipMemcpyAsync(dst ? dst : h->st, c, offsetof(DevState, vm), hipMemcpyHostToDevice,
+                           h->stream));
   return SSP_OK;
 }
 
-int read_state(ssp_handle *h, bool whole) {
+int read_state(ssp_handle *h, bool whole, const DevState *src = nullptr) {
   const size_t bytes = whole ? sizeof(DevState) : offsetof(DevState, vm);
-  HIPCHK(h, hipMemcpyAsync(h->h_read, h->st, bytes, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipMemcpyAsync(h->h_read, src ? src : h->st, bytes, hipMemcpyDeviceToHost,
+                           h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
   return SSP_OK;
 }
@@ -711,6 +747,11 @@ int ssp_create(ssp_handle **out, int device, void *stream) {
     ssp_destroy(h);
     return SSP_EHIP;
   }
+  const int rc = scratch_setup(device);
+  if (rc) {
+    ssp_destroy(h);
+    return rc;
+  }
   *out = h;
   return SSP_OK;
 }
@@ -991,7 +1032,7 @@ int ssp_mpk(ssp_handle *h, const ssp_matrix *A, const double *r, int s, double *
   if (rc) return rc;
   rc = state_init(h, s, 1, 1, 0.0, 0);
   if (rc) return rc;
-  rc = mpk_f64(s)(h, A, r, P, ld);
+  rc = mpk_f64(s)(h, A, r, P, ld, nullptr);
   if (rc) return rc;
   if (vm) {
     rc = read_state(h, true);
@@ -999,6 +1040,35 @@ int ssp_mpk(ssp_handle *h, const ssp_matrix *A, const double *r, int s, double *
     memcpy(vm, h->h_read->vm, sizeof(double) * 2 * s);
   }
   return SSP_OK;
+}
+
+int ssp_mpk_noalloc(ssp_handle *h, const ssp_matrix *A, const double *r, int s, double *P,
+                    int64_t ld, double *vm) {
+  if (!h) return SSP_EINVAL;
+  int rc = check_matrix(h, A);
+  if (rc) return rc;
+  if (!r || !P || s < 1 || s > SSP_SMAX || s > A->n || ld < A->n)
+    return fail(h, SSP_EINVAL, "ssp_mpk_noalloc: invalid arguments (s=" + std::to_string(s) + ")");
+  const int G = grid_of(A);
+  if ((size_t)G * 2 * s > kScratchPartials)
+    return fail(h, SSP_EINVAL, "ssp_mpk_noalloc: " + std::to_string(G) + " workgroups x 2s = " +
+                                   std::to_string(2 * s) + " partial sums exceed the scratch (" +
+                                   std::to_string(kScratchPartials) + ")");
+  HIPCHK(h, hipSetDevice(h->device));
+  unsigned char *base = h->device < kMaxDevices ? (unsigned char *)scratch_addr[h->device] : nullptr;
+  if (!base) return fail(h, SSP_EHIP, "ssp_mpk_noalloc: no scratch address for this device");
+  const Ctl ctl{(DevState *)base, (double *)(base + kScratchState)};
+  // no event objects may be created here: profiling is off for this call
+  const bool prof = h->prof_on;
+  h->prof_on = false;
+  rc = state_init(h, s, 1, 1, 0.0, 0, ctl.st);
+  if (!rc) rc = mpk_f64(s)(h, A, r, P, ld, &ctl);
+  if (!rc && vm) {
+    rc = read_state(h, true, ctl.st);
+    if (!rc) memcpy(vm, h->h_read->vm, sizeof(double) * 2 * s);
+  }
+  h->prof_on = prof;
+  return rc;
 }
 
 int ssp_solve(ssp_handle *h, const ssp_matrix *A, const double *b, double *x, int s, double rtol,

@@ -196,28 +196,36 @@ inline void prof_collect(ssp_handle *h, int iters_done) {
 }
 
 // Operator launch (CSR or stencil kind) with epilogue Epi, followed by the
-// finalisation kernel when Epi reduces.
+// finalisation kernel when Epi reduces.  The control block and the partial
+// sums are the handle's unless `ctl` names others (the allocation-free
+// entry point passes its static scratch).
+struct Ctl {
+  DevState *st;
+  double *partials;
+};
 template <typename T, class Epi>
 int launch_op(ssp_handle *h, const ssp_matrix *A, const T *x, const Epi &epi, int cls,
-              T xs = T(1)) {
+              T xs = T(1), const Ctl *ctl = nullptr) {
   const int G = grid_of(A);
   T *tag = nullptr;
+  DevState *const st = ctl ? ctl->st : h->st;
+  double *const partials = ctl ? ctl->partials : h->ws.partials;
   prof_begin(h, cls);
   switch (A->kind) {
     case 0:
       if (A->csr.variant == CSR_ROW)
-        k_csr<CSR_ROW, T, Epi><<<G, kWG, 0, h->stream>>>(csr_of(A, tag), x, xs, epi, h->st,
-                                                          h->ws.partials);
+        k_csr<CSR_ROW, T, Epi><<<G, kWG, 0, h->stream>>>(csr_of(A, tag), x, xs, epi, st,
+                                                          partials);
       else if (A->csr.variant == CSR_SELL)
-        k_csr<CSR_SELL, T, Epi><<<G, kWG, 0, h->stream>>>(csr_of(A, tag), x, xs, epi, h->st,
-                                                           h->ws.partials);
+        k_csr<CSR_SELL, T, Epi><<<G, kWG, 0, h->stream>>>(csr_of(A, tag), x, xs, epi, st,
+                                                           partials);
       else
-        k_csr<CSR_STAGED, T, Epi><<<G, kWG, 0, h->stream>>>(csr_of(A, tag), x, xs, epi, h->st,
-                                                             h->ws.partials);
+        k_csr<CSR_STAGED, T, Epi><<<G, kWG, 0, h->stream>>>(csr_of(A, tag), x, xs, epi, st,
+                                                             partials);
       break;
     case SSP_STENCIL_2D5:
-      k_stencil<K_2D5, T, Epi><<<G, kWG, 0, h->stream>>>(sten_of(A, tag), x, xs, epi, h->st,
-                                                          h->ws.partials);
+      k_stencil<K_2D5, T, Epi><<<G, kWG, 0, h->stream>>>(sten_of(A, tag), x, xs, epi, st,
+                                                          partials);
       break;
     case SSP_STENCIL_3D7:
     case SSP_STENCIL_3D27: {
@@ -226,29 +234,29 @@ int launch_op(ssp_handle *h, const ssp_matrix *A, const T *x, const Epi &epi, in
       if (A->kind == SSP_STENCIL_3D7) {
         if (tiled)
           k_stencil_tiled<K_3D7, T, Epi><<<G, kWG, 0, h->stream>>>(sten_of(A, tag), x, xs, epi,
-                                                                    h->st, h->ws.partials, tl);
+                                                                    st, partials, tl);
         else
-          k_stencil<K_3D7, T, Epi><<<G, kWG, 0, h->stream>>>(sten_of(A, tag), x, xs, epi, h->st,
-                                                              h->ws.partials);
+          k_stencil<K_3D7, T, Epi><<<G, kWG, 0, h->stream>>>(sten_of(A, tag), x, xs, epi, st,
+                                                              partials);
       } else {
         if (tiled)
           k_stencil_tiled<K_3D27, T, Epi><<<G, kWG, 0, h->stream>>>(sten_of(A, tag), x, xs, epi,
-                                                                     h->st, h->ws.partials, tl);
+                                                                     st, partials, tl);
         else
           k_stencil<K_3D27, T, Epi><<<G, kWG, 0, h->stream>>>(sten_of(A, tag), x, xs, epi,
-                                                               h->st, h->ws.partials);
+                                                               st, partials);
       }
       break;
     }
     case SSP_STENCIL_3D7_VARK:
-      k_stencil<K_VARK, T, Epi><<<G, kWG, 0, h->stream>>>(sten_of(A, tag), x, xs, epi, h->st,
-                                                           h->ws.partials);
+      k_stencil<K_VARK, T, Epi><<<G, kWG, 0, h->stream>>>(sten_of(A, tag), x, xs, epi, st,
+                                                           partials);
       break;
     default:
       return fail(h, SSP_EINVAL, "unknown operator kind " + std::to_string(A->kind));
   }
   if constexpr (Epi::NP > 0) {
-    k_finalize<Epi><<<1, kWG, 0, h->stream>>>(epi, h->st, h->ws.partials, G);
+    k_finalize<Epi><<<1, kWG, 0, h->stream>>>(epi, st, partials, G);
   }
   prof_end(h);
   LAUNCHCHK(h);
@@ -318,7 +326,8 @@ int sstep_iteration(ssp_handle *h, const ssp_matrix *A, const IterBufs<T> &B, in
 
 // Alg. 4 + Alg. 5 on their own (no solve): the block P and vm in the state.
 template <int S>
-int mpk_only(ssp_handle *h, const ssp_matrix *A, const double *r, double *P, int64_t ld) {
+int mpk_only(ssp_handle *h, const ssp_matrix *A, const double *r, double *P, int64_t ld,
+             const Ctl *ctl) {
   double *tag = nullptr;
   const Prec<double> pc = prec_of(A, tag);
   const int G = grid_rows(A->n);
@@ -328,8 +337,10 @@ int mpk_only(ssp_handle *h, const ssp_matrix *A, const double *r, double *P, int
     const double *zin = P + (int64_t)(j - 1) * ld;
     double *az = P + (int64_t)(S + j - 1) * ld;
     int rc;
-    if (j < S) rc = launch_op<double>(h, A, zin, EpiMpk<double>{az, P + (int64_t)j * ld, pc}, 0);
-    else rc = launch_op<double>(h, A, zin, EpiMpkLast<S, double>{az, P, ld, r, 0}, 1);
+    if (j < S)
+      rc = launch_op<double>(h, A, zin, EpiMpk<double>{az, P + (int64_t)j * ld, pc}, 0, 1.0, ctl);
+    else
+      rc = launch_op<double>(h, A, zin, EpiMpkLast<S, double>{az, P, ld, r, 0}, 1, 1.0, ctl);
     if (rc) return rc;
   }
   return SSP_OK;
@@ -337,7 +348,8 @@ int mpk_only(ssp_handle *h, const ssp_matrix *A, const double *r, double *P, int
 
 template <typename T>
 using iter_fn = int (*)(ssp_handle *, const ssp_matrix *, const IterBufs<T> &, int, bool, bool);
-using mpk_fn = int (*)(ssp_handle *, const ssp_matrix *, const double *, double *, int64_t);
+using mpk_fn = int (*)(ssp_handle *, const ssp_matrix *, const double *, double *, int64_t,
+                       const Ctl *);
 
 // Defined in inst_f64.hip (s = 1..16) and inst_f32.hip (s = 1..8);
 // nullptr for an s out of range.

@@ -39,7 +39,7 @@ EXPORTS = (
     "ssp_net_forward", "ssp_net_zero_grad", "ssp_net_backward", "ssp_net_loss",
     "ssp_net_adam_step", "ssp_net_get_state", "ssp_net_set_state", "ssp_conv3d",
     "ssp_conv3d_wgrad", "ssp_net_mfma_selftest", "ssp_get_warm_start", "ssp_get_restarts",
-    "ssp_net_loss_h1", "ssp_matrix_csr_form",
+    "ssp_net_loss_h1", "ssp_matrix_csr_form", "ssp_mpk_noalloc",
 )
 
 
@@ -105,6 +105,7 @@ def load():
         "ssp_set_preconditioner": (i32, [vp, i32]),
         "ssp_spmv": (i32, [vp, vp, vp, vp]),
         "ssp_mpk": (i32, [vp, vp, vp, i32, vp, i64, vp]),
+        "ssp_mpk_noalloc": (i32, [vp, vp, vp, i32, vp, i64, vp]),
         "ssp_solve": (i32, [vp, vp, vp, vp, i32, dbl, i32, C.POINTER(_Opts)]),
         "ssp_get_iterations": (i32, [vp, C.POINTER(i32), C.POINTER(i32)]),
         "ssp_get_residual_history": (i32, [vp, vp, i32, C.POINTER(i32)]),
@@ -337,17 +338,21 @@ class Handle:
         if rc:
             self._err(rc, "ssp_spmv")
 
-    def mpk(self, A: Matrix, r, s: int, P=None):
-        """Alg. 4 + Alg. 5: returns (P as a (2s, n) view of the block, vm)."""
+    def mpk(self, A: Matrix, r, s: int, P=None, noalloc: bool = False):
+        """Alg. 4 + Alg. 5: returns (P as a (2s, n) view of the block, vm).
+        noalloc=True calls ssp_mpk_noalloc (no device allocation in the
+        library; P must then be given)."""
         import torch
         _check_dev(r, torch.float64, A.n, "r")
         if P is None:
+            if noalloc:
+                raise ValueError("mpk(noalloc=True) needs a caller-supplied P")
             P = torch.empty((2 * s, A.n), dtype=torch.float64, device=r.device)
         vm = np.zeros(2 * s)
-        rc = load().ssp_mpk(self._h, A._p, _ptr(r), s, _ptr(P), P.stride(0),
-                            vm.ctypes.data_as(C.c_void_p))
+        fn = load().ssp_mpk_noalloc if noalloc else load().ssp_mpk
+        rc = fn(self._h, A._p, _ptr(r), s, _ptr(P), P.stride(0), vm.ctypes.data_as(C.c_void_p))
         if rc:
-            self._err(rc, "ssp_mpk")
+            self._err(rc, fn.__name__)
         return P, vm
 
     # ---------------------------------------------------------------- batches
