@@ -8,11 +8,16 @@ are resident in HBM before the timed region.  Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
-The line carries the solve time, the matrix-powers kernel's achieved HBM
-bandwidth against the 8 TB/s peak (algorithmic bytes per launch over the mean
-launch time from HIP events on the library's stream), the standard-CG and
-stencil-form times for comparison, and the CPU oracle timed on a bounded
-sample of the same solve.
+Besides the timed solves the line carries: the matrix-powers kernel's
+achieved bandwidth against the 8 TB/s HBM peak (algorithmic bytes per launch
+over the mean launch time from HIP events on the library's stream) at 128^3,
+where the matrix stays in the memory-side cache, and at 256^3, where it is
+streamed from HBM; the bandwidth of the library's own streaming read and copy
+kernels; the comparison rows of every workload (standard PCG, PFCG, each s,
+the matrix-free form, the Chebyshev basis, mixed precision); the 27-point
+256^3 problem against the oracle's FP64 solution; the batch of 32 uneven
+systems; a bounded run of the learned warm start; and the CPU oracle's full
+solves on the host cores.
 """
 from __future__ import annotations
 
@@ -36,7 +41,7 @@ SEED = 0
 MAXIT = 20000
 
 
-def algorithmic_bytes(n, nnz):
+def algorithmic_bytes(n, nnz, s=S):
     """Bytes one launch of each kernel class must move (FP64 values and
     vectors, int32 indices).  The 7-point matrix has a constant diagonal, so
     the Jacobi scaling is one constant c: no Z column of the block is stored,
@@ -45,27 +50,31 @@ def algorithmic_bytes(n, nnz):
       last power + moments: 12 nnz + 4 n + input, AZ_s, r (24 n) + AZ_1..AZ_{s-2} (8 (s-2) n)
       block update: reads AZ, P_old, AP_old, x, r (8 (3s + 2) n),
                     writes P, AP, x, r (8 (2s + 2) n)
+      Chebyshev basis, block Gram pass: reads Z, AZ, AP_old, r (8 (3s + 1) n)
     """
     return {
         "mpk": 12 * nnz + 4 * n + 16 * n,
-        "mpk_last": 12 * nnz + 4 * n + 24 * n + 8 * (S - 2) * n,
-        "update": 8 * (3 * S + 2) * n + 8 * (2 * S + 2) * n,
+        "mpk_last": 12 * nnz + 4 * n + 24 * n + 8 * (s - 2) * n,
+        "update": 8 * (3 * s + 2) * n + 8 * (2 * s + 2) * n,
+        "gram": 8 * (3 * s + 1) * n,
     }
 
 
 def kernel_source_sha():
     h = hashlib.sha256()
-    for f in ("common.hpp", "operators.hpp", "kernels.hpp", "small_solve.hpp", "engine.hpp",
-              "setup_kernels.hpp", "capi.hip"):
+    for f in ("common.hpp", "operators.hpp", "kernels.hpp", "small_solve.hpp", "gram.hpp",
+              "engine.hpp", "setup_kernels.hpp", "capi.hip"):
         with open(os.path.join(ROOT, "paper_2501_03743_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def read_traffic(sha):
-    """HBM traffic of the matrix-powers kernel from the committed rocprofv3
-    counter summary, if it was taken on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", "traffic_csr_mpk_3d7_128.txt")
+def read_traffic(name, sha, key="fetch_write_bytes_per_launch"):
+    """Bytes moved between the L2 caches and memory (FETCH_SIZE + WRITE_SIZE
+    counters, scaled by the copy calibration) per launch of a kernel, from a
+    committed rocprofv3 counter summary, if it was taken on the current
+    kernel sources; None otherwise."""
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     vals = {}
@@ -76,32 +85,90 @@ def read_traffic(sha):
     if vals.get("kernel_source_sha") != sha:
         return None
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(vals[key])
     except (KeyError, ValueError):
         return None
 
 
-def cpu_baseline(gpu_outer, budget_s=20.0):
-    """The oracle (plain C, FP64, OpenMP) on the same 128^3 CSR problem:
-    a bounded number of outer iterations, scaled to the outer-iteration count
-    of the full solve."""
+def median_time(fn, reps=5):
+    """Median wall time of `reps` runs after one warm-up (each run synchronised)."""
+    import torch
+    fn()
+    ts, out = [], None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t)
+    return float(np.median(ts)), out
+
+
+def oracle_threads():
+    import oracle
+    return oracle.set_threads(0)
+
+
+def cpu_baseline(budget_one_thread_s=40.0):
+    """The oracle (plain C, FP64, OpenMP over fixed row chunks) on the same
+    128^3 CSR problem, run to the end: the s-step solve (s = 4) with all host
+    threads (the value), the same with one thread, and standard PCG with all
+    threads.  The one-thread solve is skipped if a probe of two outer
+    iterations predicts more than `budget_one_thread_s`."""
     import oracle
     from paper_2501_03743_amd import workloads as wl
     csr = wl.stencil_csr("3d7", (N, N, N))
     op = oracle.Operator("csr", csr=csr)
     b = wl.normal_rhs(N ** 3, SEED)
-    k = 2
+    cores = oracle_threads()
     t0 = time.perf_counter()
-    oracle.sstep(op, b, S, fixed_outer=k)
-    per = (time.perf_counter() - t0) / k
-    k2 = int(max(2, min(30, budget_s / max(per, 1e-6) - k)))
+    r = oracle.sstep(op, b, S, rtol=RTOL, maxit=MAXIT)
+    t_all = time.perf_counter() - t0
     t0 = time.perf_counter()
-    oracle.sstep(op, b, S, fixed_outer=k2)
-    per = (time.perf_counter() - t0) / k2
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": per * gpu_outer, "unit": "s", "cores": cores, "kind": "oracle",
-            "sample": "%d outer iterations (s=%d) of the same 128^3 CSR solve, %.3f s each, "
-                      "scaled to the %d outer iterations of the full solve" % (k2, S, per, gpu_outer)}
+    rp = oracle.pcg(op, b, rtol=RTOL, maxit=MAXIT)
+    t_pcg = time.perf_counter() - t0
+    oracle.set_threads(1)
+    t_one = None
+    try:
+        t0 = time.perf_counter()
+        oracle.sstep(op, b, S, fixed_outer=2)
+        per = (time.perf_counter() - t0) / 2
+        if per * r.outer <= budget_one_thread_s:
+            t0 = time.perf_counter()
+            r1 = oracle.sstep(op, b, S, rtol=RTOL, maxit=MAXIT)
+            t_one = time.perf_counter() - t0
+            assert r1.outer == r.outer
+        else:
+            t_one = None
+    finally:
+        oracle.set_threads(cores)
+    return {"value": t_all, "unit": "s", "cores": cores, "kind": "oracle",
+            "sample": "the full 128^3 CSR s-step solve (s=4, rtol 1e-8, %d outer iterations) with "
+                      "%d OpenMP threads" % (r.outer, cores),
+            "one_thread_s": t_one, "pcg_all_threads_s": t_pcg, "pcg_iterations": rp.outer,
+            "outer": r.outer, "true_rel": r.true_rel}
+
+
+def oracle_small(csr0, b0):
+    """The oracle on the launch-bound 2D 64^2 problem: s-step (s = 4 and 1)
+    and standard PCG, one thread and all threads."""
+    import oracle
+    op = oracle.Operator("csr", csr=csr0)
+    cores = oracle_threads()
+    out = {"cores": cores}
+    for threads, tag in ((1, "one_thread"), (cores, "all_threads")):
+        oracle.set_threads(threads)
+        for name, fn in (("sstep_s4", lambda: oracle.sstep(op, b0, 4, rtol=RTOL)),
+                         ("sstep_s1", lambda: oracle.sstep(op, b0, 1, rtol=RTOL)),
+                         ("pcg", lambda: oracle.pcg(op, b0, rtol=RTOL))):
+            fn()
+            t0 = time.perf_counter()
+            for _ in range(5):
+                rr = fn()
+            out["%s_%s_ms" % (name, tag)] = 1e3 * (time.perf_counter() - t0) / 5
+            out["%s_iterations" % name] = rr.outer
+    oracle.set_threads(cores)
+    return out
 
 
 def bench_batch(H, count=32, lo=32, hi=160, seed=0):
@@ -137,19 +204,24 @@ def bench_batch(H, count=32, lo=32, hi=160, seed=0):
 
     batch_once()
     reps = [batch_once() for _ in range(3)]
-    t_batch = min(r[0] for r in reps)
+    t_batch = float(np.median([r[0] for r in reps]))
     _, st, it, tr = reps[-1]
-    persistent = None
-    if tune.schedule != 0:
-        from paper_2501_03743_amd import sstep
-        tp = sstep.Tune(tile_rows=tune.tile_rows, grid=1024, order=1, schedule=0)
-        for v in xs:
-            v.zero_()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        H.solve_batch(mats, bs, xs, s=S, rtol=RTOL, maxit=MAXIT, tune=tp)
-        torch.cuda.synchronize()
-        persistent = time.perf_counter() - t0
+    from paper_2501_03743_amd import sstep
+    forms = {}
+    for name, tn in (("persistent", sstep.Tune(tile_rows=tune.tile_rows, grid=tune.grid or 1024,
+                                               order=tune.order, schedule=0)),
+                     ("stepped", sstep.Tune(tile_rows=tune.tile_rows, schedule=1))):
+        ts = []
+        for _ in range(3):
+            for v in xs:
+                v.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rcn, stn, _, trn = H.solve_batch(mats, bs, xs, s=S, rtol=RTOL, maxit=MAXIT, tune=tn)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        forms[name] = {"s": float(np.median(ts)), "all_converged": bool((stn == 0).all()),
+                       "max_true_rel": float(np.max(trn))}
 
     def seq_once(precision):
         res = []
@@ -162,7 +234,9 @@ def bench_batch(H, count=32, lo=32, hi=160, seed=0):
         return time.perf_counter() - t0, res
 
     seq_once("mixed_ir")
-    t_seq, res_seq = min((seq_once("mixed_ir") for _ in range(2)), key=lambda r: r[0])
+    runs = [seq_once("mixed_ir") for _ in range(3)]
+    t_seq = float(np.median([r[0] for r in runs]))
+    res_seq = runs[-1][1]
     t_seq64, res64 = seq_once("fp64")
     out = {
         "workload": "%d x 3D 7-point variable-coefficient Poisson, L ~ U{%d..%d} (sum n = %d), "
@@ -171,10 +245,13 @@ def bench_batch(H, count=32, lo=32, hi=160, seed=0):
         "sides": sides,
         "tune": tune.as_dict(), "autotune_s": tune_s,
         "batch_s": t_batch,
-        "persistent_launch_s": persistent,
+        "persistent_launch_s": forms["persistent"]["s"],
+        "stepped_s": forms["stepped"]["s"],
+        "forms": forms,
         "sequential_mixed_s": t_seq,
         "sequential_fp64_s": t_seq64,
         "speedup_vs_sequential_mixed": t_seq / t_batch,
+        "timing": "median of 3 runs each, wall time around the call",
         "all_converged": bool((st == 0).all()) and all(r.status == 0 for r in res_seq),
         "max_true_rel_batch": float(np.max(tr)),
         "max_true_rel_sequential": float(max(r.true_rel for r in res_seq)),
@@ -243,7 +320,7 @@ def bench_paper_1e9(H):
 
 
 def bench_warmstart(H, n_train=2000, n_eval=200, side=96, epochs=40, lr=2e-3, batch=4,
-                    log=None, sweeps=16):
+                    log=None, sweeps=16, n_loose=50, n_forms=20):
     """The learned warm start on -div(k grad u) = f at side^3: log k a Gaussian
     random field (sigma 1, correlation length 0.1), f a random sum of 16
     Fourier modes; the network trained on n_train solver solutions (seeds
@@ -268,10 +345,10 @@ def bench_warmstart(H, n_train=2000, n_eval=200, side=96, epochs=40, lr=2e-3, ba
     summ = ws.summarize(rec)
     # the same held-out seeds at a looser tolerance, where a guess's share of
     # the decades CG must gain is larger
-    summ_1e6 = ws.summarize(ws.evaluate(H, model, seeds[:50], s=S, rtol=1e-6, sweeps=sweeps))
+    summ_1e6 = ws.summarize(ws.evaluate(H, model, seeds[:n_loose], s=S, rtol=1e-6, sweeps=sweeps))
     # the full forms at equal final accuracy on the first held-out seeds
     forms = {}
-    m = min(20, n_eval)
+    m = min(n_forms, n_eval)
     for name, kw, warm in (("pcg_fp64_x0_0", {"method": "pcg"}, False),
                            ("sstep_fp64_x0_0", {}, False),
                            ("sstep_mixed_x0_0", {"precision": "mixed_ir"}, False),
@@ -306,7 +383,8 @@ def bench_warmstart(H, n_train=2000, n_eval=200, side=96, epochs=40, lr=2e-3, ba
         "loss": "energy e^T (L + 1e-3 I) e", "smoothing_sweeps": sweeps,
         "generate_s": gen_s, "train_s": train_s, "loss_first": hist[0], "loss_last": hist[-1],
         "params": params,
-        "held_out": summ, "held_out_rtol_1e-6_first_50": summ_1e6, "forms_first_%d" % m: forms,
+        "held_out": summ, "held_out_rtol_1e-6_first_%d" % n_loose: summ_1e6,
+        "forms_first_%d" % m: forms,
     }
 
 
@@ -318,12 +396,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-27pt", action="store_true",
                     help="skip the 256^3 27-point FP64 / mixed-precision comparison")
+    ap.add_argument("--skip-oracle-27pt", action="store_true",
+                    help="skip the oracle's 256^3 27-point reference solve")
+    ap.add_argument("--skip-batch", action="store_true", help="skip the batched solves")
+    ap.add_argument("--skip-warmstart", action="store_true",
+                    help="skip the bounded learned-warm-start run")
     ap.add_argument("--only-timed", action="store_true",
                     help="only the timed solves (for profiler runs)")
-    ap.add_argument("--batch", action="store_true",
-                    help="add the batched-solve comparison (32 uneven variable-coefficient systems)")
     ap.add_argument("--warmstart", action="store_true",
-                    help="only the learned warm start (trains the network; several minutes)")
+                    help="only the learned warm start at its full budget (several minutes)")
     ap.add_argument("--ws-train", type=int, default=2000)
     ap.add_argument("--ws-eval", type=int, default=200)
     ap.add_argument("--ws-side", type=int, default=96)
@@ -331,6 +412,11 @@ def main():
     ap.add_argument("--csr256-outer", type=int, default=0,
                     help="only the 256^3 7-point CSR solve for this many outer iterations "
                          "(s = 4, no stopping test): a short target for counter runs")
+    ap.add_argument("--csr256-basis", default="monomial",
+                    help="basis of the --csr256-outer run (monomial or chebyshev)")
+    ap.add_argument("--csr27-outer", type=int, default=0,
+                    help="only the 27-point 256^3 CSR solve for this many outer iterations "
+                         "(s = 4, FP64, no stopping test): a short target for counter runs")
     ap.add_argument("--paper-1e9", action="store_true",
                     help="only the paper's largest problem on one GPU: 3D 7-point 1000^3 "
                          "(10^9 unknowns, stencil form), b = 1, no preconditioner, rtol 1e-6; "
@@ -340,28 +426,30 @@ def main():
                          "batch 4 (forward, energy loss, backward, Adam) and as many batch-1 "
                          "forwards: a short target for kernel-trace and MFMA counter runs")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="only a plain 1 GiB device-to-device copy, three times (the "
+                    help="only the library's plain copy of 1 GiB, three times (the "
                          "reference for the FETCH_SIZE / WRITE_SIZE counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: the library runs on one GPU (no sharding or collectives); "
-              "use --gpus 1", file=sys.stderr)
+        print("bench.py: this build runs on one GPU only (the solver has no sharding or "
+              "collectives); --gpus %d is not supported, use --gpus 1" % args.gpus,
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
     from paper_2501_03743_amd import sstep
     from paper_2501_03743_amd import workloads as wl
 
+    def log(m):
+        print("[bench] " + m, file=sys.stderr, flush=True)
+
     torch.cuda.set_device(0)
+    H = sstep.Handle(0)
     if args.copy_calibration:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes": src.numel() * 8, "copies": 3}))
+        ms = H.stream_probe(src, dst, reps=3)
+        print(json.dumps({"copy_bytes": src.numel() * 8, "copies": 4, "ms_per_copy": ms}))
         return
-    H = sstep.Handle(0)
     if args.net_steps > 0:
         print(json.dumps({"net_steps": bench_net_steps(H, args.net_steps)}))
         return
@@ -373,15 +461,25 @@ def main():
         A3 = H.matrix_csr_from_stencil("3d7", (N3, N3, N3))
         b3 = torch.from_numpy(wl.normal_rhs(N3 ** 3, SEED)).cuda()
         x3 = torch.zeros_like(b3)
-        r3 = H.solve(A3, b3, x3, s=S, fixed_outer=args.csr256_outer, profile=True)
+        r3 = H.solve(A3, b3, x3, s=S, fixed_outer=args.csr256_outer, profile=True,
+                     basis=args.csr256_basis)
         print(json.dumps({"workload": "3D 7-point 256^3 CSR", "csr_form": A3.csr_form,
-                          "nnz": A3.nnz, "outer": r3.outer, "profile": r3.profile}))
+                          "basis": args.csr256_basis, "nnz": A3.nnz, "outer": r3.outer,
+                          "profile": r3.profile}))
+        return
+    if args.csr27_outer > 0:
+        N2 = 256
+        A2 = H.matrix_csr_from_stencil("3d27", (N2, N2, N2))
+        b2 = torch.from_numpy(wl.normal_rhs(N2 ** 3, SEED)).cuda()
+        x2 = torch.zeros_like(b2)
+        r2 = H.solve(A2, b2, x2, s=S, fixed_outer=args.csr27_outer, profile=True)
+        print(json.dumps({"workload": "3D 27-point 256^3 CSR", "csr_form": A2.csr_form,
+                          "nnz": A2.nnz, "outer": r2.outer, "profile": r2.profile}))
         return
     if args.warmstart:
-        def log(m):
-            print("[warmstart] " + m, file=sys.stderr, flush=True)
         print(json.dumps({"config_warm_start": bench_warmstart(
-            H, args.ws_train, args.ws_eval, args.ws_side, args.ws_epochs, log=log)}))
+            H, args.ws_train, args.ws_eval, args.ws_side, args.ws_epochs,
+            log=lambda m: log("warmstart: " + m))}))
         return
     n = N ** 3
     A = H.matrix_csr_from_stencil("3d7", (N, N, N))
@@ -408,43 +506,106 @@ def main():
     if args.only_timed:
         print(json.dumps({"tts_s": tts, "outer": res.outer}))
         return
+    log("headline: %.2f ms per solve, %d outer iterations" % (1e3 * tts, res.outer))
 
     # kernel durations from HIP events on the library's stream (same solves, profiled)
-    prof_ms = np.zeros(4)
-    prof_n = np.zeros(4)
-    for _ in range(args.steps):
-        r = solve(profile=True)
-        prof_ms += np.array(r.profile["ms"])
-        prof_n += np.array(r.profile["launches"])
+    def profile_means(fn, reps):
+        ms = np.zeros(sstep.PROFILE_CLASSES)
+        cnt = np.zeros(sstep.PROFILE_CLASSES)
+        for _ in range(reps):
+            r = fn()
+            ms += np.array(r.profile["ms"])
+            cnt += np.array(r.profile["launches"])
+        return ms / np.maximum(cnt, 1), cnt / reps, ms / reps
+
+    mean_ms, launches, per_solve_ms = profile_means(lambda: solve(profile=True), args.steps)
     nnz = A.nnz
     ab = algorithmic_bytes(n, nnz)
-    mpk_ms = prof_ms[0] / max(prof_n[0], 1)
-    last_ms = prof_ms[1] / max(prof_n[1], 1)
-    upd_ms = prof_ms[2] / max(prof_n[2], 1)
-    achieved = ab["mpk"] / (mpk_ms * 1e-3) / 1e9
+    achieved = ab["mpk"] / (mean_ms[0] * 1e-3) / 1e9
     sha = kernel_source_sha()
-    traffic = read_traffic(sha)
+    traffic = read_traffic("traffic_csr_mpk_3d7_128.txt", sha)
 
-    # comparisons (outside the timed region): standard CG, the stencil form, other s
-    def timed(fn, reps=3):
-        fn()
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(reps):
-            rr = fn()
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t) / reps, rr
+    # achievable bandwidth: the library's own streaming read and copy of 1 GiB
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    read_gbs = src.numel() * 8 / (H.stream_probe(src, reps=10) * 1e-3) / 1e9
+    copy_gbs = 2 * src.numel() * 8 / (H.stream_probe(src, dst, reps=10) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    log("stream probe: read %.0f GB/s, copy %.0f GB/s" % (read_gbs, copy_gbs))
 
-    cg_t, cg_r = timed(lambda: solve(method="pcg"))
-    pf_t, pf_r = timed(lambda: solve(method="pfcg"))
-    mx_t, mx_r = timed(lambda: solve(precision="mixed_ir"))
+    # matrix powers at 256^3 (the 1.4 GB sliced-ELL matrix does not fit the 256 MB
+    # memory-side cache): per-launch rates over 10 profiled outer iterations
+    N3 = 256
+    n3 = N3 ** 3
+    A3 = H.matrix_csr_from_stencil("3d7", (N3, N3, N3))
+    b3 = torch.from_numpy(wl.normal_rhs(n3, SEED)).cuda()
+    x3 = torch.zeros_like(b3)
+    H.solve(A3, b3, x3, s=S, fixed_outer=2)
+    x3.zero_()
+    r3 = H.solve(A3, b3, x3, s=S, fixed_outer=10, profile=True)
+    ab3 = algorithmic_bytes(n3, A3.nnz)
+    m3 = np.array(r3.profile["ms"]) / np.maximum(np.array(r3.profile["launches"]), 1)
+    mpk3_gbs = ab3["mpk"] / (m3[0] * 1e-3) / 1e9
+    big = {"workload": "3D 7-point 256^3 CSR (n=16777216, nnz=%d), s=4, 10 outer iterations"
+                       % A3.nnz,
+           "mpk_gbs": mpk3_gbs, "mpk_frac_of_peak": mpk3_gbs / HBM_PEAK_GBS,
+           "mpk_last_gbs": ab3["mpk_last"] / (m3[1] * 1e-3) / 1e9,
+           "update_gbs": ab3["update"] / (m3[2] * 1e-3) / 1e9,
+           "mpk_mean_launch_ms": m3[0]}
+    # the Chebyshev basis at 256^3: the block Gram pass on the FP64 matrix cores
+    cheb_gram = {}
+    for sc in (4, 8):
+        x3.zero_()
+        rc3 = H.solve(A3, b3, x3, s=sc, fixed_outer=6, profile=True, basis="chebyshev")
+        mc = np.array(rc3.profile["ms"]) / np.maximum(np.array(rc3.profile["launches"]), 1)
+        gb = algorithmic_bytes(n3, A3.nnz, sc)["gram"]
+        cheb_gram["s%d" % sc] = {"gram_ms": mc[4], "gram_bytes": gb,
+                                 "gram_gbs": gb / (mc[4] * 1e-3) / 1e9,
+                                 "gram_frac_of_peak": gb / (mc[4] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                 "gram_fp64_flops": 2 * sc * (2 * sc + 1) * n3}
+    big["chebyshev_gram_pass"] = cheb_gram
+    A3.close()
+    del b3, x3
+    torch.cuda.empty_cache()
+    log("256^3 matrix power %.0f GB/s" % mpk3_gbs)
+
+    # comparisons at 128^3 (outside the timed region; medians of 5 solves)
+    compare = {}
+
+    def row(fn):
+        t, r = median_time(fn)
+        return {"tts_s": t, "outer": r.outer, "cg_equiv": r.cg_equiv, "status": r.status,
+                "true_rel": r.true_rel, "restarts": r.restarts}
+
+    compare["pcg_csr"] = row(lambda: solve(method="pcg"))
+    compare["pfcg_csr"] = row(lambda: solve(method="pfcg"))
+    compare["sstep_mixed_ir_csr"] = row(lambda: solve(precision="mixed_ir"))
+    per_s = {}
+    for sv in (1, 2, 4, 8):
+        per_s[str(sv)] = row(lambda: solve(s=sv))
+    per_s["8_restarts"] = row(lambda: solve(s=8, restarts=3))
+    compare["sstep_csr_by_s"] = per_s
+    cheb = {}
+    for sv in (4, 8, 12, 16):
+        cheb[str(sv)] = row(lambda: solve(s=sv, basis="chebyshev"))
+    cheb["8_mixed_ir"] = row(lambda: solve(s=8, basis="chebyshev", precision="mixed_ir"))
+    compare["sstep_csr_chebyshev_by_s"] = cheb
     As = H.matrix_stencil("3d7", (N, N, N))
+
     def solve_st(**kw):
         x.zero_()
         return H.solve(As, b, x, rtol=RTOL, maxit=MAXIT, **kw)
-    st_t, st_r = timed(lambda: solve_st(s=S))
-    stcg_t, stcg_r = timed(lambda: solve_st(method="pcg"))
-    stpf_t, stpf_r = timed(lambda: solve_st(method="pfcg"))
+
+    st_s = {}
+    for sv in (1, 2, 4, 8):
+        st_s[str(sv)] = row(lambda: solve_st(s=sv))
+    st_s["8_chebyshev"] = row(lambda: solve_st(s=8, basis="chebyshev"))
+    st_s["4_mixed_ir"] = row(lambda: solve_st(s=4, precision="mixed_ir"))
+    compare["sstep_stencil_by_s"] = st_s
+    compare["pcg_stencil"] = row(lambda: solve_st(method="pcg"))
+    compare["pfcg_stencil"] = row(lambda: solve_st(method="pfcg"))
+
     # plain SpMV per operator form / CSR kernel variant (HIP events on the same stream)
     def spmv_ms(M, reps=20):
         y = torch.empty_like(b)
@@ -473,119 +634,115 @@ def main():
     spmv["csr_best_gbs"] = plain_bytes / (min(spmv["csr_staged_ms"], spmv["csr_row_ms"],
                                               spmv["csr_sell_ms"]) * 1e-3) / 1e9
     spmv["stencil_gbs"] = 16 * n / (spmv["stencil_ms"] * 1e-3) / 1e9
-
-    # achievable bandwidth: a device-to-device copy of 1 GiB (read + write)
-    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(5):
-        dst.copy_(src)
-    e1.record()
-    torch.cuda.synchronize()
-    copy_gbs = 2 * src.numel() * 8 / (e0.elapsed_time(e1) / 5 * 1e-3) / 1e9
-    del src, dst
-
-    # matrix powers at 256^3 (the 1.4 GB CSR matrix does not fit the 256 MB
-    # Infinity Cache): per-launch HBM rate over 10 profiled outer iterations
-    N3 = 256
-    A3 = H.matrix_csr_from_stencil("3d7", (N3, N3, N3))
-    b3 = torch.from_numpy(wl.normal_rhs(N3 ** 3, SEED)).cuda()
-    x3 = torch.zeros_like(b3)
-    H.solve(A3, b3, x3, s=S, fixed_outer=2)
-    x3.zero_()
-    r3 = H.solve(A3, b3, x3, s=S, fixed_outer=10, profile=True)
-    ab3 = algorithmic_bytes(N3 ** 3, A3.nnz)
-    mpk3_ms = r3.profile["ms"][0] / max(r3.profile["launches"][0], 1)
-    upd3_ms = r3.profile["ms"][2] / max(r3.profile["launches"][2], 1)
-    big = {"workload": "3D 7-point 256^3 CSR (n=16777216), s=4, 10 outer iterations",
-           "mpk_gbs": ab3["mpk"] / (mpk3_ms * 1e-3) / 1e9,
-           "mpk_frac_of_peak": ab3["mpk"] / (mpk3_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-           "update_gbs": ab3["update"] / (upd3_ms * 1e-3) / 1e9}
-    A3.close()
-    del b3, x3
+    compare["spmv"] = spmv
+    As.close()
+    log("128^3 comparisons done")
 
     # 2D 5-point 64^2 (everything cache-resident, launch-bound): x* ~ U(-1,1)
-    # from seeds 0..4, b = A x*, s = 4, standard PCG and PFCG
+    # from seeds 0..4, b = A x*; medians of 5 solves per form
     small = []
-    A0 = H.matrix_csr(*[torch.from_numpy(a).cuda() for a in wl.stencil_csr("2d5", (64, 64))],
-                      flags=sstep.COPY)
     csr0 = wl.stencil_csr("2d5", (64, 64))
+    A0 = H.matrix_csr(*[torch.from_numpy(a).cuda() for a in csr0], flags=sstep.COPY)
+    b0_seed0 = None
     for seed in range(5):
-        b0 = torch.from_numpy(wl.csr_matvec(csr0, wl.uniform_solution(64 * 64, seed))).cuda()
-        row = {"seed": seed}
-        for name, kw in (("sstep", {"s": S}), ("pcg", {"method": "pcg"}),
+        b0h = wl.csr_matvec(csr0, wl.uniform_solution(64 * 64, seed))
+        if seed == 0:
+            b0_seed0 = b0h
+        b0 = torch.from_numpy(b0h).cuda()
+        rw = {"seed": seed}
+        x0 = torch.zeros_like(b0)
+        for name, kw in (("sstep_s4", {"s": 4}), ("sstep_s1", {"s": 1}), ("pcg", {"method": "pcg"}),
                          ("pfcg", {"method": "pfcg"})):
-            x0 = torch.zeros_like(b0)
-            H.solve(A0, b0, x0, rtol=RTOL, **kw)
-            x0.zero_()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            rr = H.solve(A0, b0, x0, rtol=RTOL, **kw)
-            torch.cuda.synchronize()
-            row[name + "_ms"] = 1e3 * (time.perf_counter() - t0)
-            row[name + "_iterations"] = rr.cg_equiv if name == "sstep" else rr.outer
-        small.append(row)
+            def one(kw=kw):
+                x0.zero_()
+                return H.solve(A0, b0, x0, rtol=RTOL, **kw)
+            t, rr = median_time(one)
+            rw[name + "_ms"] = 1e3 * t
+            rw[name + "_iterations"] = rr.cg_equiv if name.startswith("sstep") else rr.outer
+        small.append(rw)
     A0.close()
-
-    per_s = {}
-    for s in (1, 2, 8):
-        t, r = timed(lambda: solve(s=s), reps=2)
-        per_s[str(s)] = {"tts_s": t, "outer": r.outer, "status": r.status,
-                         "true_rel": r.true_rel}
-    # s = 8 drifts from the true residual; residual replacement by restart
-    t, r = timed(lambda: solve(s=8, restarts=3), reps=2)
-    per_s["8_restarts"] = {"tts_s": t, "outer": r.outer, "status": r.status,
-                           "true_rel": r.true_rel, "restarts": r.restarts}
+    config0 = {"workload": "2D 5-point 64^2 (n=4096), CSR, Jacobi, x* ~ U(-1,1) seeds 0..4, "
+                           "b = A x*, rtol 1e-8", "rows": small}
+    if not args.no_cpu_baseline:
+        config0["oracle_seed0"] = oracle_small(csr0, b0_seed0)
 
     # 3D 27-point 256^3 (n = 16.8M, 449M stored entries), Jacobi, s = 4, to rtol 1e-10:
-    # plain FP64 s-step and standard CG versus the FP32-inner / FP64-refinement form;
-    # errors against an FP64 s-step solve to rtol 1e-13 (which the parity tests tie to
-    # the oracle at smaller sizes)
+    # plain FP64 s-step and standard CG versus the FP32-inner / FP64-refinement form,
+    # CSR and matrix-free; each x compared with the oracle's FP64 solution
+    # (27-point stencil form, all host threads, rtol 1e-10)
     config2 = None
     if not args.skip_27pt:
         N2 = 256
-        A2 = H.matrix_csr_from_stencil("3d27", (N2, N2, N2))
-        b2 = torch.from_numpy(wl.normal_rhs(N2 ** 3, SEED)).cuda()
+        n2 = N2 ** 3
+        b2h = wl.normal_rhs(n2, SEED)
+        b2 = torch.from_numpy(b2h).cuda()
         x2 = torch.zeros_like(b2)
-        xref = torch.zeros_like(b2)
-        rref = H.solve(A2, b2, xref, s=S, rtol=1e-13, maxit=MAXIT)
+        xo = None
+        config2 = {"workload": "3D 27-point 256^3 (n=16777216), Jacobi, s=4, b~N(0,1) seed 0, "
+                               "rtol 1e-10", "reference": None}
+        if not args.skip_oracle_27pt:
+            import oracle
+            t0 = time.perf_counter()
+            ro = oracle.sstep(oracle.Operator("3d27", (N2, N2, N2)), b2h, S, rtol=1e-10,
+                              maxit=MAXIT)
+            config2["reference"] = {"kind": "oracle", "form": "27-point stencil", "s": S,
+                                    "rtol": 1e-10, "outer": ro.outer, "status": ro.status,
+                                    "true_rel": ro.true_rel, "host_s": time.perf_counter() - t0,
+                                    "threads": oracle_threads()}
+            xo = torch.from_numpy(ro.x).cuda()
+            del ro
+            log("27-point oracle reference: %.1f s" % config2["reference"]["host_s"])
 
-        def run2(**kw):
+        def run2(M, **kw):
             x2.zero_()
             torch.cuda.synchronize()
             t = time.perf_counter()
-            rr = H.solve(A2, b2, x2, rtol=1e-10, maxit=MAXIT, **kw)
+            rr = H.solve(M, b2, x2, rtol=1e-10, maxit=MAXIT, **kw)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t
-            err = float(torch.linalg.vector_norm(x2 - xref) / torch.linalg.vector_norm(xref))
-            return {"tts_s": dt, "status": rr.status, "outer": rr.outer, "true_rel": rr.true_rel,
-                    "rel_err_vs_fp64_ref": err, "refinements": len(rr.hist) - 1}
-        run2(s=S, precision="mixed_ir")   # first use builds the FP32 copy
-        config2 = {"workload": "3D 27-point 256^3 (n=16777216, nnz=%d), CSR, Jacobi, s=4, "
-                               "b~N(0,1) seed 0, rtol 1e-10" % A2.nnz,
-                   "fp64_ref_true_rel": rref.true_rel,
-                   "sstep_fp64": run2(s=S),
-                   "sstep_mixed_ir": run2(s=S, precision="mixed_ir"),
-                   "sstep_mixed_ir_inner1e-6": run2(s=S, precision="mixed_ir", inner_rtol=1e-6),
-                   "sstep_mixed_ir_inner1e-4": run2(s=S, precision="mixed_ir", inner_rtol=1e-4),
-                   "pcg_fp64": run2(method="pcg")}
+            out = {"tts_s": dt, "status": rr.status, "outer": rr.outer,
+                   "true_rel": rr.true_rel}
+            if kw.get("precision") == "mixed_ir":
+                out["refinements"] = len(rr.hist) - 1
+            if xo is not None:
+                out["rel_err_vs_oracle"] = float(torch.linalg.vector_norm(x2 - xo) /
+                                                 torch.linalg.vector_norm(xo))
+            return out
+
+        A2 = H.matrix_csr_from_stencil("3d27", (N2, N2, N2))
+        config2["nnz"] = A2.nnz
+        run2(A2, s=S, precision="mixed_ir")   # first use builds the FP32 copy
+        config2["csr_sstep_fp64"] = run2(A2, s=S)
+        config2["csr_sstep_mixed_ir"] = run2(A2, s=S, precision="mixed_ir")
+        config2["csr_sstep_mixed_ir_inner1e-6"] = run2(A2, s=S, precision="mixed_ir",
+                                                       inner_rtol=1e-6)
+        config2["csr_pcg_fp64"] = run2(A2, method="pcg")
         A2.close()
+        torch.cuda.empty_cache()
         # the same operator matrix-free (nothing stored but the two coefficients)
         A2 = H.matrix_stencil("3d27", (N2, N2, N2))
-        run2(s=S, precision="mixed_ir")
-        config2["stencil_sstep_fp64"] = run2(s=S)
-        config2["stencil_sstep_mixed_ir"] = run2(s=S, precision="mixed_ir")
-        config2["stencil_pcg_fp64"] = run2(method="pcg")
+        run2(A2, s=S, precision="mixed_ir")
+        config2["stencil_sstep_fp64"] = run2(A2, s=S)
+        config2["stencil_sstep_mixed_ir"] = run2(A2, s=S, precision="mixed_ir")
+        config2["stencil_pcg_fp64"] = run2(A2, method="pcg")
         A2.close()
-        del b2, x2, xref
+        del b2, x2, xo
+        torch.cuda.empty_cache()
+        log("27-point 256^3 done")
 
     config3 = None
-    if args.batch:
+    if not args.skip_batch:
         config3 = {"batch32_L32_160": bench_batch(H),
                    "batch128_L12_40": bench_batch(H, count=128, lo=12, hi=40, seed=1)}
+        log("batches done")
+
+    config4 = None
+    if not args.skip_warmstart:
+        # bounded: 400 training solutions, 24 epochs, 50 held-out seeds
+        config4 = bench_warmstart(H, n_train=400, n_eval=50, epochs=24, n_loose=20, n_forms=20,
+                                  log=lambda m: log("warmstart: " + m))
+        config4["budget"] = "bounded: 400 training solutions, 24 epochs, 50 held-out seeds"
+        log("warm start done")
 
     out = {
         "metric": "time-to-solution @rtol 1e-8 (s) + SpMV/matrix-powers HBM GB/s, s-step vs CG",
@@ -607,38 +764,41 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "matrix-powers CSR SpMV + Jacobi (power j < s)",
-                     "bytes_per_launch": ab["mpk"], "mean_launch_ms": mpk_ms},
+                     "note": "the 176 MB sliced-ELL matrix stays in the 256 MB memory-side "
+                             "cache at 128^3; roofline_hbm_resident is the same kernel at "
+                             "256^3, streamed from HBM",
+                     "bytes_per_launch": ab["mpk"], "mean_launch_ms": mean_ms[0]},
+        "roofline_hbm_resident": {
+            "bound": "hbm", "achieved": mpk3_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": mpk3_gbs / HBM_PEAK_GBS,
+            "traffic": read_traffic("traffic_csr_mpk_3d7_256.txt", sha),
+            "kernel": "matrix-powers CSR SpMV + Jacobi (power j < s), 3D 7-point 256^3",
+            "bytes_per_launch": ab3["mpk"], "mean_launch_ms": m3[0]},
+        "achievable": {"stream_read_gbs": read_gbs, "stream_copy_gbs": copy_gbs,
+                       "mpk_frac_of_read": achieved / read_gbs,
+                       "mpk256_frac_of_read": mpk3_gbs / read_gbs,
+                       "kernels": "libsstep k_stream_read / k_stream_copy, 1 GiB"},
         "iterations": {"outer": res.outer, "cg_equiv": res.cg_equiv, "true_rel": res.true_rel},
         "kernels": {
             "mpk_gbs": achieved,
-            "mpk_last_gram_solve_ms": last_ms,
-            "mpk_last_gbs": ab["mpk_last"] / (last_ms * 1e-3) / 1e9,
-            "update_ms": upd_ms,
-            "update_gbs": ab["update"] / (upd_ms * 1e-3) / 1e9,
-            "kernel_ms_per_solve": (prof_ms / args.steps).tolist(),
-            "launches_per_solve": (prof_n / args.steps).tolist(),
+            "mpk_last_gram_solve_ms": mean_ms[1],
+            "mpk_last_gbs": ab["mpk_last"] / (mean_ms[1] * 1e-3) / 1e9,
+            "update_ms": mean_ms[2],
+            "update_gbs": ab["update"] / (mean_ms[2] * 1e-3) / 1e9,
+            "kernel_ms_per_solve": per_solve_ms.tolist(),
+            "launches_per_solve": launches.tolist(),
             "kernel_source_sha": sha,
         },
-        "compare": {
-            "pcg_csr_tts_s": cg_t, "pcg_csr_iterations": cg_r.outer,
-            "sstep_stencil_tts_s": st_t, "sstep_stencil_outer": st_r.outer,
-            "pcg_stencil_tts_s": stcg_t, "pcg_stencil_iterations": stcg_r.outer,
-            "pfcg_csr_tts_s": pf_t, "pfcg_csr_iterations": pf_r.outer,
-            "sstep_mixed_ir_csr_tts_s": mx_t, "sstep_mixed_ir_csr_outer": mx_r.outer,
-            "sstep_mixed_ir_csr_true_rel": mx_r.true_rel,
-            "pfcg_stencil_tts_s": stpf_t, "pfcg_stencil_iterations": stpf_r.outer,
-            "sstep_csr_by_s": per_s,
-            "spmv": spmv,
-            "copy_gbs": copy_gbs,
-            "mpk_frac_of_copy": achieved / copy_gbs,
-            "csr_3d7_256": big,
-            "config_2d5_64": small,
-        },
+        "compare": compare,
+        "csr_3d7_256": big,
+        "config_2d5_64": config0,
         "config_27pt_256_mixed": config2,
         "config_batch32": config3,
+        "config_warm_start": config4,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(res.outer)
+        out["cpu_baseline"] = cpu_baseline()
+        log("cpu baseline: %.2f s" % out["cpu_baseline"]["value"])
     print(json.dumps(out))
 
 

@@ -75,6 +75,15 @@ typedef struct ssp_matrix ssp_matrix;
 #define SSP_METHOD_PFCG 2     /* Alg. 2: flexible PCG with one reduction per
                                  step (the paper's comparator); s is ignored    */
 
+#define SSP_BASIS_MONOMIAL 0   /* Alg. 4's basis [z, Kz, ..., K^{s-1} z] with
+                                 Alg. 5's 2s moments and Alg. 6                 */
+#define SSP_BASIS_CHEBYSHEV 1  /* z_{j+1} = T_j((K - cI)/h) z over an interval
+                                 [lo, hi] = [c - h, c + h] enclosing the
+                                 spectrum of K = B^-1 A (the stabilised bases of
+                                 the related work, Sec. IV); the s x (2s+1)
+                                 inner products Z^T [AZ | AP_{i-1} | r] are
+                                 formed in one pass on the FP64 matrix cores    */
+
 #define SSP_PRECISION_FP64 0
 #define SSP_PRECISION_MIXED_IR 1  /* FP32 inner s-step (matrix powers and block
                                      updates in FP32, moments and s x s solves
@@ -121,6 +130,12 @@ typedef struct ssp_opts {
                           run starts with its true residual); see
                           ssp_get_restarts.  MIXED_IR ignores it: its
                           refinement loop already ends on the true residual   */
+  int basis;           /* SSP_BASIS_* (s-step method, FP64 and MIXED_IR)         */
+  double basis_lo;     /* Chebyshev basis interval; basis_hi <= basis_lo selects
+                          the default [0, 2] with the Jacobi preconditioner and
+                          [0, 2 max_i a_ii] without one (Gershgorin, for a
+                          weakly diagonally dominant SPD matrix)               */
+  double basis_hi;
 } ssp_opts;
 
 /* ---- handle ---------------------------------------------------------------- */
@@ -192,6 +207,18 @@ int ssp_spmv(ssp_handle *h, const ssp_matrix *A, const double *x, double *y);
 int ssp_mpk(ssp_handle *h, const ssp_matrix *A, const double *r, int s, double *P,
             int64_t ld, double *vm);
 
+/* The Chebyshev basis of one outer iteration (SSP_BASIS_CHEBYSHEV; the
+ * stabilised bases of the related work, Sec. IV) on its own: fills the DEVICE
+ * block P (column-major, leading dimension ld >= n, even; P and r 16-byte
+ * aligned; 2s columns) with Z = [z_1 .. z_s], z_1 = B^-1 r, z_2 = (K z_1 - c z_1)/h,
+ * z_{j+1} = 2 (K z_j - c z_j)/h - z_{j-1} (K = B^-1 A, c = (hi + lo)/2,
+ * h = (hi - lo)/2; hi <= lo selects the default interval of ssp_opts), and
+ * P(:,s+1:2s) = A Z; and, if gram is a non-NULL HOST pointer, the block Gram
+ * product of the matrix cores, gram = Z^T [AZ | r] (s x (s+1), row-major)
+ * (synchronises). */
+int ssp_cheb_basis(ssp_handle *h, const ssp_matrix *A, const double *r, int s, double lo,
+                   double hi, double *P, int64_t ld, double *gram);
+
 /* ssp_mpk without any device allocation, for callers that cannot allocate
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc).  Same arguments, kernels and results (bit for bit) as ssp_mpk.
@@ -245,11 +272,14 @@ int ssp_get_true_residual(const ssp_handle *h, double *rel);
 
 /* Kernel-class timings of the last solve run with opts.profile = 1, measured
  * with HIP events on the handle's stream: for each class the number of
- * launches and the summed duration in milliseconds (HOST arrays of 4).
- * Classes: 0 = matrix powers j < s (Alg. 4; SpMV of standard CG),
- * 1 = last power fused with the moments (Alg. 5) and the s x s solve
- * (Alg. 6), 2 = block update (Alg. 3; vector updates of standard CG),
- * 3 = other (initial and true residual). */
+ * launches and the summed duration in milliseconds (HOST arrays of
+ * SSP_PROFILE_CLASSES).  Classes: 0 = matrix powers j < s (Alg. 4; SpMV of
+ * standard CG), 1 = last power fused with the moments (Alg. 5) and the s x s
+ * solve (Alg. 6; on the Chebyshev basis the last power and the s x s
+ * algebra), 2 = block update (Alg. 3; vector updates of standard CG),
+ * 3 = other (initial and true residual), 4 = the block Gram pass of the
+ * Chebyshev basis. */
+#define SSP_PROFILE_CLASSES 5
 int ssp_get_profile(const ssp_handle *h, int *launches, double *ms);
 
 /* ---- batched solves ---------------------------------------------------------- */
@@ -372,6 +402,14 @@ int ssp_conv3d_wgrad(ssp_handle *h, const float *x, int B, int D, int H, int W, 
 /* One 16x16x32 BF16 matrix-core product D = A B with the operand layout the
  * convolutions use (DEVICE FP32 row-major A 16x32, B 32x16, D 16x16). */
 int ssp_net_mfma_selftest(ssp_handle *h, const float *A, const float *B, float *D);
+
+/* Roofline reference: the mean duration (*ms, milliseconds, HIP events on
+ * the handle's stream, after one warm-up launch) of `reps` launches of a
+ * plain streaming read of the n doubles at src (mode 0) or a copy src -> dst
+ * (mode 1), 16-byte accesses over the library's largest launch grid.  DEVICE
+ * pointers, 16-byte aligned; n even.  Synchronises. */
+int ssp_stream_probe(ssp_handle *h, int mode, const double *src, double *dst, int64_t n,
+                     int reps, double *ms);
 
 /* Text for a status code (static storage). */
 const char *ssp_status_string(int status);

@@ -5,6 +5,7 @@
 #include <mutex>
 
 #include "engine.hpp"
+#include "measure.hpp"
 #include "setup_kernels.hpp"
 
 using namespace ssp;
@@ -133,10 +134,14 @@ int64_t block_ld(int64_t n, int64_t align, int64_t elem_bytes) {
   return (n + align - 1) / align * align + kColumnStagger / elem_bytes;
 }
 
-int ensure_workspace(ssp_handle *h, int64_t n, int s, int hist_need, bool pcg) {
+int ensure_workspace(ssp_handle *h, int64_t n, int s, int hist_need, bool pcg,
+                     bool gram = false) {
   Workspace &w = h->ws;
   if (!w.partials) HIPCHK(h, hipMalloc(&w.partials, sizeof(double) * kGridMax * 2 * kSMax));
   if (!w.partials_rr) HIPCHK(h, hipMalloc(&w.partials_rr, sizeof(double) * kGridMax));
+  if (gram && !w.partials_gram)
+    HIPCHK(h, hipMalloc(&w.partials_gram,
+                        sizeof(double) * kGramGrid * kSMax * (2 * kSMax + 1)));
   if (n > w.n || s > w.s) {
     hfree_t(w.P1);
     hfree_t(w.P2);
@@ -483,12 +488,63 @@ int warm_start_judge(ssp_handle *h, const ssp_matrix *A, const double *b, double
   return SSP_OK;
 }
 
+// Largest diagonal entry of A, from the Jacobi data built at set-up (the
+// default Chebyshev interval without a preconditioner).
+int max_diagonal(ssp_handle *h, const ssp_matrix *A, double &dmax) {
+  if (A->kind != 0 && A->kind != SSP_STENCIL_3D7_VARK) {
+    dmax = A->sten.diag;
+    return SSP_OK;
+  }
+  if (!A->dinv) {
+    dmax = 1.0 / A->dconst;
+    return SSP_OK;
+  }
+  // the first word of the (idle) partial-sum buffer holds the maximum's bits
+  unsigned long long *d = reinterpret_cast<unsigned long long *>(h->ws.partials);
+  HIPCHK(h, hipMemsetAsync(d, 0, sizeof(unsigned long long), h->stream));
+  const unsigned nb = (unsigned)std::min<int64_t>((A->n + kWG - 1) / kWG, kGridMax);
+  k_max_recip<<<nb, kWG, 0, h->stream>>>(A->n, A->dinv, d);
+  LAUNCHCHK(h);
+  unsigned long long bits = 0;
+  HIPCHK(h, hipMemcpyAsync(&bits, d, sizeof(bits), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  memcpy(&dmax, &bits, sizeof(dmax));
+  return SSP_OK;
+}
+
+// Centre c and inverse half-width g of the Chebyshev basis interval.
+int cheb_params(ssp_handle *h, const ssp_matrix *A, const ssp_opts *o, double &c, double &g) {
+  double lo = o ? o->basis_lo : 0.0, hi = o ? o->basis_hi : 0.0;
+  if (!(hi > lo)) {
+    lo = 0.0;
+    if (A->prec == SSP_PREC_JACOBI) {
+      hi = 2.0;
+    } else {
+      double dmax = 0.0;
+      const int rc = max_diagonal(h, A, dmax);
+      if (rc) return rc;
+      hi = 2.0 * dmax;
+    }
+  }
+  if (!std::isfinite(lo) || !std::isfinite(hi) || !(hi > lo))
+    return fail(h, SSP_EINVAL, "Chebyshev basis: invalid interval");
+  c = 0.5 * (hi + lo);
+  g = 1.0 / (0.5 * (hi - lo));
+  return SSP_OK;
+}
+
 int solve_sstep(ssp_handle *h, const ssp_matrix *A, const double *b, double *x, int s,
                 double rtol, int maxit, const ssp_opts *o) {
   const int fixed = (o && o->fixed_outer > 0) ? o->fixed_outer : 0;
   const int outer_max = fixed ? fixed : (int)((maxit + (int64_t)s - 1) / s);
-  int rc = ensure_workspace(h, A->n, s, outer_max + 1, false);
+  const bool cheb = o && o->basis == SSP_BASIS_CHEBYSHEV;
+  int rc = ensure_workspace(h, A->n, s, outer_max + 1, false, cheb);
   if (rc) return rc;
+  double cc = 0.0, cg = 0.0;
+  if (cheb) {
+    rc = cheb_params(h, A, o, cc, cg);
+    if (rc) return rc;
+  }
   Workspace &w = h->ws;
   rc = state_init(h, s, outer_max, fixed ? 1 : 0, rtol, w.hist_cap);
   if (rc) return rc;
@@ -496,8 +552,8 @@ int solve_sstep(ssp_handle *h, const ssp_matrix *A, const double *b, double *x, 
   // r = b - A x0 and z1 = B^-1 r into column 1 of the block used at k = 0
   rc = launch_op<double>(h, A, x, EpiInit{b, w.r, w.P2, prec_of(A, tag), w.hist}, 3);
   if (rc) return rc;
-  const iter_fn<double> step = iteration_f64(s);
-  const IterBufs<double> B{w.P1, w.P2, w.ld, x, w.r};
+  const iter_fn<double> step = cheb ? cheb_iteration_f64(s) : iteration_f64(s);
+  const IterBufs<double> B{w.P1, w.P2, w.ld, x, w.r, cc, cg};
   const int trace_cap = (o && o->trace_cap > 0 && o->trace_vm && o->trace_alpha &&
                          o->trace_beta && o->trace_W) ? o->trace_cap : 0;
   int every = (o && o->check_every > 0) ? o->check_every : std::max(1, 32 / s);
@@ -635,8 +691,14 @@ int solve_mixed(ssp_handle *h, ssp_matrix *A, const double *b, double *x, int s,
   const double inner_rtol = (o && o->inner_rtol > 0.0) ? o->inner_rtol : 1e-5;
   const int max_refine = (o && o->max_refine > 0) ? o->max_refine : 10;
   const int inner_max = (int)((maxit + (int64_t)s - 1) / s);
-  int rc = ensure_workspace(h, A->n, 1, std::max(max_refine + 1, inner_max + 1), false);
+  const bool cheb = o && o->basis == SSP_BASIS_CHEBYSHEV;
+  int rc = ensure_workspace(h, A->n, 1, std::max(max_refine + 1, inner_max + 1), false, cheb);
   if (rc) return rc;
+  double cc = 0.0, cg = 0.0;
+  if (cheb) {
+    rc = cheb_params(h, A, o, cc, cg);
+    if (rc) return rc;
+  }
   rc = ensure_workspace32(h, A->n, s);
   if (rc) return rc;
   rc = ensure_fp32(h, A);
@@ -657,8 +719,8 @@ int solve_mixed(ssp_handle *h, ssp_matrix *A, const double *b, double *x, int s,
   }
   float *tag32 = nullptr;
   const Prec<float> pc32 = prec_of(A, tag32);
-  const iter_fn<float> step = iteration_f32(s);
-  const IterBufs<float> B{w.Q1, w.Q2, w.ld32, w.d32, w.r32};
+  const iter_fn<float> step = cheb ? cheb_iteration_f32(s) : iteration_f32(s);
+  const IterBufs<float> B{w.Q1, w.Q2, w.ld32, w.d32, w.r32, cc, cg};
   const int every = (o && o->check_every > 0) ? o->check_every : std::max(1, 32 / s);
   int total_outer = 0, refine = 0, final_status = ST_MAXIT;
   for (refine = 0; refine <= max_refine; ++refine) {
@@ -773,6 +835,7 @@ int ssp_destroy(ssp_handle *h) {
   hfree_t(w.d32);
   hfree_t(w.partials);
   hfree_t(w.partials_rr);
+  hfree_t(w.partials_gram);
   hfree_t(w.hist);
   hfree_t(h->st);
   if (h->batch_mem) (void)hipFree(h->batch_mem);
@@ -1042,6 +1105,42 @@ int ssp_mpk(ssp_handle *h, const ssp_matrix *A, const double *r, int s, double *
   return SSP_OK;
 }
 
+int ssp_cheb_basis(ssp_handle *h, const ssp_matrix *A, const double *r, int s, double lo,
+                   double hi, double *P, int64_t ld, double *gram) {
+  if (!h) return SSP_EINVAL;
+  int rc = check_matrix(h, A);
+  if (rc) return rc;
+  if (!r || !P || s < 1 || s > SSP_SMAX || s > A->n || ld < A->n || (ld % 2) != 0)
+    return fail(h, SSP_EINVAL, "ssp_cheb_basis: invalid arguments (s=" + std::to_string(s) + ")");
+  if (((uintptr_t)P % 16) != 0 || ((uintptr_t)r % 16) != 0)
+    return fail(h, SSP_EINVAL, "ssp_cheb_basis: P and r must be 16-byte aligned");
+  HIPCHK(h, hipSetDevice(h->device));
+  rc = ensure_workspace(h, 1, 1, 1, false, true);
+  if (rc) return rc;
+  ssp_opts o{};
+  o.basis_lo = lo;
+  o.basis_hi = hi;
+  double c = 0.0, g = 0.0;
+  rc = cheb_params(h, A, &o, c, g);
+  if (rc) return rc;
+  rc = state_init(h, s, 1, 1, 0.0, 0);
+  if (rc) return rc;
+  double *out = h->ws.partials_rr;   // s (2s+1) <= kGridMax totals
+  rc = cheb_basis_f64(s)(h, A, r, P, ld, c, g, out);
+  if (rc) return rc;
+  if (gram) {
+    std::vector<double> t((size_t)s * (2 * s + 1));
+    HIPCHK(h, hipMemcpyAsync(t.data(), out, sizeof(double) * t.size(), hipMemcpyDeviceToHost,
+                             h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    for (int a = 0; a < s; ++a) {
+      for (int q = 0; q < s; ++q) gram[a * (s + 1) + q] = t[(size_t)a * (2 * s + 1) + q];
+      gram[a * (s + 1) + s] = t[(size_t)a * (2 * s + 1) + 2 * s];
+    }
+  }
+  return SSP_OK;
+}
+
 int ssp_mpk_noalloc(ssp_handle *h, const ssp_matrix *A, const double *r, int s, double *P,
                     int64_t ld, double *vm) {
   if (!h) return SSP_EINVAL;
@@ -1090,10 +1189,15 @@ int ssp_solve(ssp_handle *h, const ssp_matrix *A, const double *b, double *x, in
     return fail(h, SSP_EUNSUPPORTED, "ssp_solve: mixed precision is implemented for the s-step method");
   const int restarts = opts ? opts->restarts : 0;
   if (restarts < 0) return fail(h, SSP_EINVAL, "ssp_solve: restarts must be >= 0");
+  const int basis = opts ? opts->basis : SSP_BASIS_MONOMIAL;
+  if (basis != SSP_BASIS_MONOMIAL && basis != SSP_BASIS_CHEBYSHEV)
+    return fail(h, SSP_EINVAL, "ssp_solve: unknown basis " + std::to_string(basis));
+  if (basis == SSP_BASIS_CHEBYSHEV && method != SSP_METHOD_SSTEP)
+    return fail(h, SSP_EUNSUPPORTED, "ssp_solve: the Chebyshev basis is for the s-step method");
   HIPCHK(h, hipSetDevice(h->device));
   h->prof_on = opts && opts->profile;
   h->ev_used = 0;
-  for (int c = 0; c < 4; ++c) {
+  for (int c = 0; c < SSP_PROFILE_CLASSES; ++c) {
     h->prof_launch[c] = 0;
     h->prof_ms[c] = 0.0;
   }
@@ -1169,9 +1273,42 @@ int ssp_get_true_residual(const ssp_handle *h, double *rel) {
   return SSP_OK;
 }
 
+int ssp_stream_probe(ssp_handle *h, int mode, const double *src, double *dst, int64_t n,
+                     int reps, double *ms) {
+  if (!h || !src || !ms || n < 2 || (n % 2) != 0 || reps < 1 || (mode != 0 && mode != 1) ||
+      (mode == 1 && !dst) || ((uintptr_t)src % 16) != 0 || (dst && ((uintptr_t)dst % 16) != 0))
+    return h ? fail(h, SSP_EINVAL, "ssp_stream_probe: invalid arguments") : SSP_EINVAL;
+  HIPCHK(h, hipSetDevice(h->device));
+  int rc = ensure_workspace(h, 1, 1, 1, false);
+  if (rc) return rc;
+  hipEvent_t e0, e1;
+  HIPCHK(h, hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(h, SSP_EHIP, "ssp_stream_probe: event creation failed");
+  }
+  auto launch = [&]() {
+    if (mode == 0) k_stream_read<<<kGridMax, kWG, 0, h->stream>>>(n, src, h->ws.partials);
+    else k_stream_copy<<<kGridMax, kWG, 0, h->stream>>>(n, src, dst);
+  };
+  launch();   // warm-up
+  (void)hipEventRecord(e0, h->stream);
+  for (int i = 0; i < reps; ++i) launch();
+  (void)hipEventRecord(e1, h->stream);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float t = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return fail(h, SSP_EHIP, std::string("ssp_stream_probe: ") + hipGetErrorString(e));
+  *ms = (double)t / reps;
+  return SSP_OK;
+}
+
 int ssp_get_profile(const ssp_handle *h, int *launches, double *ms) {
   if (!h) return SSP_EINVAL;
-  for (int c = 0; c < 4; ++c) {
+  for (int c = 0; c < SSP_PROFILE_CLASSES; ++c) {
     if (launches) launches[c] = h->prof_launch[c];
     if (ms) ms[c] = h->prof_ms[c];
   }

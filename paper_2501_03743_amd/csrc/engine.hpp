@@ -13,6 +13,7 @@
 #include <string>
 #include <vector>
 
+#include "gram.hpp"
 #include "kernels.hpp"
 #include "sstep.h"
 
@@ -31,6 +32,7 @@ struct Workspace {
   float *r32 = nullptr, *d32 = nullptr;
   double *partials = nullptr;              // kGridMax x 2*kSMax
   double *partials_rr = nullptr;           // kGridMax: the block update's ||r||^2
+  double *partials_gram = nullptr;         // kGramGrid x s(2s+1): the block Gram pass
   double *hist = nullptr;
   int hist_cap = 0;
 };
@@ -59,8 +61,8 @@ struct ssp_handle {
   std::vector<int> ev_iter;        // outer iteration of the launch (-1: outside the loop)
   int prof_iter = -1;
   size_t ev_used = 0;
-  int prof_launch[4] = {0, 0, 0, 0};
-  double prof_ms[4] = {0, 0, 0, 0};
+  int prof_launch[SSP_PROFILE_CLASSES] = {};
+  double prof_ms[SSP_PROFILE_CLASSES] = {};
   // batched solves: one device buffer for every per-system array
   void *batch_mem = nullptr;
   size_t batch_bytes = 0;
@@ -156,7 +158,8 @@ inline int grid_of(const ssp_matrix *A) {
 }
 
 // Profiling classes: 0 matrix powers j < s and plain SpMV, 1 last power with
-// moments and s x s solve, 2 vector/block updates, 3 other.
+// moments and s x s solve, 2 vector/block updates, 3 other, 4 the block Gram
+// pass of the Chebyshev basis.
 inline void prof_begin(ssp_handle *h, int cls) {
   if (!h->prof_on) return;
   if (h->ev_used + 2 > h->ev.size()) {
@@ -269,6 +272,7 @@ struct IterBufs {
   T *P1, *P2;       // ping-pong n x 2s blocks
   int64_t ld;
   T *x, *r;
+  double cheb_c = 0.0, cheb_g = 0.0;   // Chebyshev basis: centre, 1 / half-width
 };
 
 // One outer iteration of the s-step method (Alg. 3): s matrix-power
@@ -324,6 +328,62 @@ int sstep_iteration(ssp_handle *h, const ssp_matrix *A, const IterBufs<T> &B, in
   return SSP_OK;
 }
 
+// One outer iteration on the Chebyshev basis: s operator launches (the basis
+// recurrence in their epilogues; the last stores AZ(:,s) only), the block
+// Gram pass on the matrix cores, its finalisation (the previous update's
+// stopping test within a polling batch, then the s x s algebra) and Alg. 3's
+// block update with the Z columns stored.
+inline int gram_grid(int64_t n) {
+  const int64_t steps = (n + kGramRows - 1) / kGramRows;
+  int64_t g = (steps + kWG / kWave - 1) / (kWG / kWave);
+  if (g > kGramGrid) g = kGramGrid;
+  return (int)std::max<int64_t>(g, 1);
+}
+
+template <int S, typename T>
+int sstep_cheb_iteration(ssp_handle *h, const ssp_matrix *A, const IterBufs<T> &B, int k,
+                         bool first_in_batch, bool last_in_batch) {
+  T *Pc = (k % 2 == 0) ? B.P2 : B.P1;
+  T *Po = (k % 2 == 0) ? B.P1 : B.P2;
+  T *tag = nullptr;
+  const Prec<T> pc = prec_of(A, tag);
+  const T c = (T)B.cheb_c, g = (T)B.cheb_g, g2 = (T)(2.0 * B.cheb_g);
+  for (int j = 1; j <= S; ++j) {
+    T *zj = Pc + (int64_t)(j - 1) * B.ld;
+    T *az = Pc + (int64_t)(S + j - 1) * B.ld;
+    int rc;
+    if (j < S)
+      rc = launch_op<T>(h, A, zj,
+                        EpiCheb<T>{az, Pc + (int64_t)j * B.ld, zj,
+                                   j >= 2 ? Pc + (int64_t)(j - 2) * B.ld : nullptr, pc, c,
+                                   j == 1 ? g : g2},
+                        0);
+    else
+      rc = launch_op<T>(h, A, zj, EpiMpk<T>{az, nullptr, pc}, 1);
+    if (rc) return rc;
+  }
+  const int Gg = gram_grid(A->n);
+  const int G = grid_rows(A->n);
+  prof_begin(h, 4);
+  k_gram<S, T><<<Gg, kWG, 0, h->stream>>>(A->n, B.ld, Pc, Po, B.r, k == 0 ? 1 : 0, h->st,
+                                           h->ws.partials_gram);
+  prof_end(h);
+  prof_begin(h, 1);
+  k_gram_finalize<S><<<1, kFinWG, 0, h->stream>>>(
+      h->st, h->ws.partials_gram, Gg, first_in_batch ? nullptr : h->ws.partials_rr, G,
+      h->ws.hist);
+  prof_end(h);
+  prof_begin(h, 2);
+  k_update<S, T><<<G, kWG, 0, h->stream>>>(A->n, B.ld, Pc, Po, B.x, B.r, pc, T(0), h->st,
+                                            h->ws.partials_rr);
+  if (last_in_batch)
+    k_finalize<FinUpdate><<<1, kWG, 0, h->stream>>>(FinUpdate{h->ws.hist}, h->st,
+                                                    h->ws.partials_rr, G);
+  prof_end(h);
+  LAUNCHCHK(h);
+  return SSP_OK;
+}
+
 // Alg. 4 + Alg. 5 on their own (no solve): the block P and vm in the state.
 template <int S>
 int mpk_only(ssp_handle *h, const ssp_matrix *A, const double *r, double *P, int64_t ld,
@@ -346,15 +406,52 @@ int mpk_only(ssp_handle *h, const ssp_matrix *A, const double *r, double *P, int
   return SSP_OK;
 }
 
+// The Chebyshev basis of one outer iteration on its own: P = [Z | AZ] for
+// z_1 = B^-1 r (columns at P + j ld), and the Gram sums Z^T [AZ | 0 | r]
+// reduced into `out` (s (2s+1) doubles, device; the AP_{i-1} part is 0).
+template <int S>
+int cheb_basis_only(ssp_handle *h, const ssp_matrix *A, const double *r, double *P, int64_t ld,
+                    double c, double g, double *out) {
+  double *tag = nullptr;
+  const Prec<double> pc = prec_of(A, tag);
+  k_prec<double><<<grid_rows(A->n), kWG, 0, h->stream>>>(A->n, r, P, pc);
+  LAUNCHCHK(h);
+  for (int j = 1; j <= S; ++j) {
+    double *zj = P + (int64_t)(j - 1) * ld;
+    double *az = P + (int64_t)(S + j - 1) * ld;
+    int rc;
+    if (j < S)
+      rc = launch_op<double>(h, A, zj,
+                             EpiCheb<double>{az, P + (int64_t)j * ld, zj,
+                                             j >= 2 ? P + (int64_t)(j - 2) * ld : nullptr, pc,
+                                             c, j == 1 ? g : 2.0 * g},
+                             0);
+    else
+      rc = launch_op<double>(h, A, zj, EpiMpk<double>{az, nullptr, pc}, 1);
+    if (rc) return rc;
+  }
+  const int Gg = gram_grid(A->n);
+  k_gram<S, double><<<Gg, kWG, 0, h->stream>>>(A->n, ld, P, nullptr, r, 1, h->st,
+                                                h->ws.partials_gram);
+  k_gram_totals<S><<<1, kFinWG, 0, h->stream>>>(h->ws.partials_gram, Gg, out);
+  LAUNCHCHK(h);
+  return SSP_OK;
+}
+
 template <typename T>
 using iter_fn = int (*)(ssp_handle *, const ssp_matrix *, const IterBufs<T> &, int, bool, bool);
+using cheb_basis_fn = int (*)(ssp_handle *, const ssp_matrix *, const double *, double *, int64_t,
+                              double, double, double *);
 using mpk_fn = int (*)(ssp_handle *, const ssp_matrix *, const double *, double *, int64_t,
                        const Ctl *);
 
 // Defined in inst_f64.hip (s = 1..16) and inst_f32.hip (s = 1..8);
-// nullptr for an s out of range.
+// nullptr for an s out of range.  cheb_*: the Chebyshev-basis iteration.
 iter_fn<double> iteration_f64(int s);
 iter_fn<float> iteration_f32(int s);
+iter_fn<double> cheb_iteration_f64(int s);
+cheb_basis_fn cheb_basis_f64(int s);
+iter_fn<float> cheb_iteration_f32(int s);
 mpk_fn mpk_f64(int s);
 
 constexpr int kSMaxF32 = 8;

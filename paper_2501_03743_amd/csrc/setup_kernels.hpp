@@ -111,6 +111,33 @@ __global__ __launch_bounds__(kWG) void k_all_equal(int64_t n, const double *__re
   if (__double_as_longlong(v[i]) != __double_as_longlong(v[0])) atomicOr(differs, 1);
 }
 
+// Largest 1 / dinv_i (the largest diagonal entry) over the finite positive
+// values, as the bit pattern of a non-negative double (which orders like the
+// integer): one atomicMax per workgroup on *out (zeroed by the caller).
+__global__ __launch_bounds__(kWG) void k_max_recip(int64_t n, const double *__restrict__ dinv,
+                                                   unsigned long long *out) {
+  double m = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * kWG) {
+    const double d = 1.0 / dinv[i];
+    if (isfinite(d) && d > m) m = d;
+  }
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    const double o = __shfl_xor(m, off, kWave);
+    m = o > m ? o : m;
+  }
+  __shared__ double red[kWG / kWave];
+  if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b = red[0];
+    for (int w = 1; w < kWG / kWave; ++w) b = red[w] > b ? red[w] : b;
+    unsigned long long bits;
+    memcpy(&bits, &b, sizeof(bits));
+    atomicMax(out, bits);
+  }
+}
+
 // Longest row of a CSR matrix (one atomicMax per workgroup).
 __global__ __launch_bounds__(kWG) void k_csr_maxrow(int64_t n, const int32_t *rowptr,
                                                     int *out) {

@@ -27,6 +27,8 @@ BORROW, COPY, VALIDATE = 0, 1, 2
 PREC = {"none": 0, "jacobi": 1}
 METHOD = {"sstep": 0, "pcg": 1, "pfcg": 2}
 PRECISION = {"fp64": 0, "mixed_ir": 1}
+BASIS = {"monomial": 0, "chebyshev": 1}
+PROFILE_CLASSES = 5
 
 # C symbols declared in include/sstep.h (checked by the CPU tests)
 EXPORTS = (
@@ -39,7 +41,8 @@ EXPORTS = (
     "ssp_net_forward", "ssp_net_zero_grad", "ssp_net_backward", "ssp_net_loss",
     "ssp_net_adam_step", "ssp_net_get_state", "ssp_net_set_state", "ssp_conv3d",
     "ssp_conv3d_wgrad", "ssp_net_mfma_selftest", "ssp_get_warm_start", "ssp_get_restarts",
-    "ssp_net_loss_h1", "ssp_matrix_csr_form", "ssp_mpk_noalloc",
+    "ssp_net_loss_h1", "ssp_matrix_csr_form", "ssp_mpk_noalloc", "ssp_cheb_basis",
+    "ssp_stream_probe",
 )
 
 
@@ -66,7 +69,8 @@ class _Opts(C.Structure):
                 ("trace_vm", C.c_void_p), ("trace_alpha", C.c_void_p),
                 ("trace_beta", C.c_void_p), ("trace_W", C.c_void_p),
                 ("warm_start", C.c_int), ("warm_sweeps", C.c_int),
-                ("warm_omega", C.c_double), ("restarts", C.c_int)]
+                ("warm_omega", C.c_double), ("restarts", C.c_int),
+                ("basis", C.c_int), ("basis_lo", C.c_double), ("basis_hi", C.c_double)]
 
 
 _lib = None
@@ -106,6 +110,8 @@ def load():
         "ssp_spmv": (i32, [vp, vp, vp, vp]),
         "ssp_mpk": (i32, [vp, vp, vp, i32, vp, i64, vp]),
         "ssp_mpk_noalloc": (i32, [vp, vp, vp, i32, vp, i64, vp]),
+        "ssp_cheb_basis": (i32, [vp, vp, vp, i32, dbl, dbl, vp, i64, vp]),
+        "ssp_stream_probe": (i32, [vp, i32, vp, vp, i64, i32, C.POINTER(dbl)]),
         "ssp_solve": (i32, [vp, vp, vp, vp, i32, dbl, i32, C.POINTER(_Opts)]),
         "ssp_get_iterations": (i32, [vp, C.POINTER(i32), C.POINTER(i32)]),
         "ssp_get_residual_history": (i32, [vp, vp, i32, C.POINTER(i32)]),
@@ -355,6 +361,33 @@ class Handle:
             self._err(rc, fn.__name__)
         return P, vm
 
+    def cheb_basis(self, A: Matrix, r, s: int, interval=None, P=None):
+        """The Chebyshev basis of one outer iteration and its block Gram
+        product: returns (P as a (2s, n) view [Z; AZ], gram = Z^T [AZ | r],
+        an s x (s+1) array)."""
+        import torch
+        _check_dev(r, torch.float64, A.n, "r")
+        if P is None:
+            ld = (A.n + 1) // 2 * 2
+            P = torch.empty((2 * s, ld), dtype=torch.float64, device=r.device)[:, :A.n]
+        gram = np.zeros((s, s + 1))
+        lo, hi = interval if interval else (0.0, 0.0)
+        rc = load().ssp_cheb_basis(self._h, A._p, _ptr(r), s, lo, hi, _ptr(P), P.stride(0),
+                                   gram.ctypes.data_as(C.c_void_p))
+        if rc:
+            self._err(rc, "ssp_cheb_basis")
+        return P, gram
+
+    def stream_probe(self, src, dst=None, reps: int = 10) -> float:
+        """Mean milliseconds of a plain streaming read of src (dst None) or a
+        copy src -> dst, timed on the device (the roofline reference)."""
+        ms = C.c_double()
+        rc = load().ssp_stream_probe(self._h, 0 if dst is None else 1, _ptr(src), _ptr(dst),
+                                     src.numel(), reps, C.byref(ms))
+        if rc:
+            self._err(rc, "ssp_stream_probe")
+        return ms.value
+
     # ---------------------------------------------------------------- batches
     def _batch_arrays(self, mats, bs, xs=None):
         import torch
@@ -405,7 +438,8 @@ class Handle:
               max_refine: int = 10, check_every: int = 0, fixed_outer: int = 0,
               profile: bool = False, trace_cap: int = 0,
               warm_start: bool = False, warm_sweeps: int = 0,
-              warm_omega: float = 0.0, restarts: int = 0) -> SolveResult:
+              warm_omega: float = 0.0, restarts: int = 0, basis: str = "monomial",
+              interval=None) -> SolveResult:
         """ssp_solve: A x = b on the device (x holds x0 on entry, the solution on
         return).  method: "sstep" (Alg. 3-6, block size s), "pcg" (Alg. 1) or
         "pfcg" (Alg. 2); precision: "fp64" or "mixed_ir" (s-step only: FP32
@@ -413,7 +447,9 @@ class Handle:
         runs exactly that many outer iterations; restarts > 0 re-runs an FP64
         method from x while its true residual misses rtol; warm_start judges
         the given x (after warm_sweeps damped Jacobi sweeps) and falls back to
-        x = 0 when ||b - A x|| >= ||b||.  Returns the status (0 converged,
+        x = 0 when ||b - A x|| >= ||b||; basis "chebyshev" (s-step only) uses
+        the Chebyshev basis over `interval` = (lo, hi) (default: the library's
+        Gershgorin interval).  Returns the status (0 converged,
         1 not converged, 2 breakdown), iteration counts, residual history and
         true residual; raises SspError on invalid arguments."""
         import torch
@@ -423,7 +459,9 @@ class Handle:
                   max_refine=max_refine, check_every=check_every, fixed_outer=fixed_outer,
                   profile=1 if profile else 0, trace_cap=0,
                   warm_start=1 if warm_start else 0, warm_sweeps=warm_sweeps,
-                  warm_omega=warm_omega, restarts=restarts)
+                  warm_omega=warm_omega, restarts=restarts, basis=BASIS[basis],
+                  basis_lo=interval[0] if interval else 0.0,
+                  basis_hi=interval[1] if interval else 0.0)
         trace = None
         if trace_cap > 0:
             trace = dict(vm=np.zeros((trace_cap, 2 * s)), alpha=np.zeros((trace_cap, s)),
@@ -448,8 +486,8 @@ class Handle:
         lib.ssp_get_true_residual(self._h, C.byref(tr))
         prof = None
         if profile:
-            launches = (C.c_int * 4)()
-            ms = (C.c_double * 4)()
+            launches = (C.c_int * PROFILE_CLASSES)()
+            ms = (C.c_double * PROFILE_CLASSES)()
             lib.ssp_get_profile(self._h, launches, ms)
             prof = dict(launches=list(launches), ms=list(ms))
         if trace is not None:
