@@ -41,15 +41,17 @@ int ensure_fp32(ssp_handle *h, ssp_matrix *A) {
                               A->csr.sell_col, nullptr, A->csr.slice_off, A->csr.slice_w,
                               A->csr.nslices,
                               A->sell_entries * (int64_t)(sizeof(float) + sizeof(int32_t)) >
-                                  kInfinityCache};
+                                  kInfinityCache,
+                              A->csr.sell_wmax};
     if (A->sell_val) {
       const int64_t ne = A->sell_entries;
-      if (hipMalloc(&A->sell_val32, sizeof(float) * ne) != hipSuccess) {
+      if (hipMalloc(&A->sell_val32, sizeof(float) * (ne + kSellPad * kWave)) != hipSuccess) {
         (void)hipGetLastError();
         return fail(h, SSP_ENOMEM, "FP32 sliced-ELL allocation failed");
       }
       k_to_float<<<(unsigned)((ne + kWG - 1) / kWG), kWG, 0, h->stream>>>(ne, A->sell_val,
                                                                            A->sell_val32);
+      HIPCHK(h, hipMemsetAsync(A->sell_val32 + ne, 0, sizeof(float) * kSellPad * kWave, h->stream));
       LAUNCHCHK(h);
       A->csr32.sell_val = A->sell_val32;
     }
@@ -348,7 +350,9 @@ int csr_build_sell(ssp_handle *h, ssp_matrix *A) {
     (void)hipFree(w);
     return SSP_OK;
   }
-  const int64_t alloc = std::max<int64_t>(tot, 1);
+  // padding of kSellPad entries per lane after the last slice: the
+  // narrow-slice kernel reads as many entries of every slice as the widest has
+  const int64_t alloc = tot + kSellPad * kWave;
   if (hipMalloc(&A->slice_off, sizeof(int64_t) * ns) != hipSuccess ||
       hipMalloc(&A->sell_col, sizeof(int32_t) * alloc) != hipSuccess ||
       hipMalloc(&A->sell_val, sizeof(double) * alloc) != hipSuccess) {
@@ -361,6 +365,8 @@ int csr_build_sell(ssp_handle *h, ssp_matrix *A) {
   }
   A->slice_w = w;
   A->sell_entries = tot;
+  HIPCHK(h, hipMemsetAsync(A->sell_col + tot, 0, sizeof(int32_t) * kSellPad * kWave, h->stream));
+  HIPCHK(h, hipMemsetAsync(A->sell_val + tot, 0, sizeof(double) * kSellPad * kWave, h->stream));
   HIPCHK(h, hipMemcpyAsync(A->slice_off, off.data(), sizeof(int64_t) * ns, hipMemcpyHostToDevice,
                            h->stream));
   k_sell_fill<<<(unsigned)((ns * kWave + kWG - 1) / kWG), kWG, 0, h->stream>>>(
@@ -374,6 +380,8 @@ int csr_build_sell(ssp_handle *h, ssp_matrix *A) {
   A->csr.slice_w = A->slice_w;
   A->csr.nslices = ns;
   A->csr.sell_xcd = tot * (int64_t)(sizeof(double) + sizeof(int32_t)) > kInfinityCache;
+  A->csr.sell_wmax = 0;
+  for (int64_t i = 0; i < ns; ++i) A->csr.sell_wmax = std::max(A->csr.sell_wmax, (int)hw[i]);
   return SSP_OK;
 }
 
