@@ -16,7 +16,7 @@ constexpr int kGridMax = 2048;    // workgroups of a streaming launch (8 per CU)
 constexpr int64_t kColumnStagger = 17 * 256;  // bytes added to block leading dimensions
 constexpr int kCsrLds = 4096;     // FP64 products staged in LDS per CSR row block
 constexpr int kCsrRowsMax = 1024; // rows per CSR row block
-constexpr int kSellPad = 8;       // padding entries (per lane) after the last sliced-ELL slice
+constexpr int kSellPad = 32;      // padding entries (per lane) after the last sliced-ELL slice
 
 // Solve status kept on the device.
 enum : int {

@@ -220,9 +220,9 @@ __device__ __forceinline__ V sell_ld(const V *p) {
 }
 
 // Slice widths with a dedicated straight-line kernel (sell_rows_narrow): the
-// 2D 5-point and 3D 7-point operators.  0 = none (the general loop).
+// 2D 5-point, 3D 7-point and 27-point operators.  0 = none (the general loop).
 __host__ __device__ constexpr int sell_narrow_width(int wmax) {
-  return (wmax == 5 || wmax == 7) ? wmax : 0;
+  return (wmax == 5 || wmax == 7 || wmax == 27) ? wmax : 0;
 }
 
 // Sliced-ELL product for a matrix whose widest slice has exactly UW entries
@@ -230,7 +230,8 @@ __host__ __device__ constexpr int sell_narrow_width(int wmax) {
 // no branch in between, the column loads of both, their value loads, their
 // gathers, then the sums and stores; a step leaves no load in flight, so the
 // compiler's wait counts stay tight (the general loop, whose column prefetch
-// crosses iterations, ends each slice waiting for every load).  Entry u of a
+// crosses iterations, ends each slice waiting for every load).  27-entry
+// slices go one per step (their 81 loaded values fill the registers).  Entry u of a
 // slice is read at the compile-time offset u * 64 from the slice's start:
 // for a slice narrower than UW the entries past its width lie in the next
 // slice, or in the kSellPad padding entries after the last one -- valid
@@ -238,7 +239,8 @@ __host__ __device__ constexpr int sell_narrow_width(int wmax) {
 // the same terms, order and rounding as the CSR product.  A matrix larger
 // than the memory-side cache takes the slices grid-strided (the GPU streams
 // one window of the arrays; measured at 256^3, 7-point: 352 -> 330 us per
-// matrix power, with the launch capped at 1024 workgroups).
+// matrix power, with the launch capped at 1024 workgroups; 27-point:
+// 1243 -> 1106 us).
 constexpr int kSellPair = 2;
 template <bool NT, int PAIR, int UW, typename T, class Pre, class F>
 __device__ __forceinline__ void sell_rows_narrow(const CsrArgs<T> &A, const T *__restrict__ x,
@@ -422,6 +424,9 @@ __device__ __forceinline__ void csr_rows(const CsrArgs<T> &A, const T *__restric
     if (nw == 7) {
       if (A.sell_xcd) sell_rows_narrow<true, kSellPair, 7>(A, x, pre, f, xs);
       else sell_rows_narrow<false, kSellPair, 7>(A, x, pre, f, xs);
+    } else if (nw == 27) {
+      if (A.sell_xcd) sell_rows_narrow<true, 1, 27>(A, x, pre, f, xs);
+      else sell_rows_narrow<false, 1, 27>(A, x, pre, f, xs);
     } else if (nw == 5) {
       if (A.sell_xcd) sell_rows_narrow<true, kSellPair, 5>(A, x, pre, f, xs);
       else sell_rows_narrow<false, kSellPair, 5>(A, x, pre, f, xs);
