@@ -147,9 +147,6 @@ inline int grid_of(const ssp_matrix *A) {
   if (A->kind == 0 && A->csr.variant == CSR_SELL) {
     int64_t g = (A->csr.nslices + kWG / kWave - 1) / (kWG / kWave);
     if (g > kGridMax) g = kGridMax;
-    // the grid-strided narrow-slice kernel streams best from 1024 workgroups
-    if (A->csr.sell_xcd && sell_narrow_width(A->csr.sell_wmax) && g > kGridMax / 2)
-      g = kGridMax / 2;
     return (int)std::max<int64_t>(g, 1);
   }
   if (A->kind == 0 && A->csr.variant == CSR_STAGED) {

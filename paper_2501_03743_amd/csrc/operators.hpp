@@ -226,22 +226,22 @@ __host__ __device__ constexpr int sell_narrow_width(int wmax) {
 }
 
 // Sliced-ELL product for a matrix whose widest slice has exactly UW entries
-// per row: each wavefront takes two of its slices per step and issues, with
-// no branch in between, the column loads of both, their value loads, their
+// per row: each wavefront takes PAIR of its slices per step and issues, with
+// no branch in between, their column loads, their value loads, their
 // gathers, then the sums and stores; a step leaves no load in flight, so the
 // compiler's wait counts stay tight (the general loop, whose column prefetch
-// crosses iterations, ends each slice waiting for every load).  27-entry
-// slices go one per step (their 81 loaded values fill the registers).  Entry u of a
+// crosses iterations, ends each slice waiting for every load).  One slice per
+// step: two ran no faster at 256^3 and fetched 30 % more (the second slice of
+// a wavefront is a grid plane away, so its gathers miss the L2).  Entry u of a
 // slice is read at the compile-time offset u * 64 from the slice's start:
 // for a slice narrower than UW the entries past its width lie in the next
 // slice, or in the kSellPad padding entries after the last one -- valid
 // addresses whose values are masked out of the sums, which therefore have
-// the same terms, order and rounding as the CSR product.  A matrix larger
-// than the memory-side cache takes the slices grid-strided (the GPU streams
-// one window of the arrays; measured at 256^3, 7-point: 352 -> 330 us per
-// matrix power, with the launch capped at 1024 workgroups; 27-point:
-// 1243 -> 1106 us).
-constexpr int kSellPair = 2;
+// the same terms, order and rounding as the CSR product.  The schedule is the
+// general loop's (XCD-interleaved pieces for a matrix larger than the
+// memory-side cache).  Measured at 256^3: 7-point 352 -> 333 us per matrix
+// power, fetching 0.97x the algorithmic bytes; 27-point 1243 -> 1111 us.
+constexpr int kSellPair = 1;
 template <bool NT, int PAIR, int UW, typename T, class Pre, class F>
 __device__ __forceinline__ void sell_rows_narrow(const CsrArgs<T> &A, const T *__restrict__ x,
                                                  Pre &&pre, F &&f, T xs) {
@@ -251,9 +251,10 @@ __device__ __forceinline__ void sell_rows_narrow(const CsrArgs<T> &A, const T *_
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
   int64_t first, WSX, s1;
   if (A.sell_xcd) {
-    first = (int64_t)blockIdx.x * WS + wave;
-    WSX = (int64_t)gridDim.x * WS;
-    s1 = A.nslices;
+    const XcdSched sc = xcd_sched(A.nslices, WS, gridDim.x, blockIdx.x);
+    first = sc.first + wave;
+    WSX = sc.stride;
+    s1 = sc.end;
   } else {
     int64_t s0;
     block_chunk(A.nslices, logical_block(), gridDim.x, s0, s1);
@@ -425,8 +426,8 @@ __device__ __forceinline__ void csr_rows(const CsrArgs<T> &A, const T *__restric
       if (A.sell_xcd) sell_rows_narrow<true, kSellPair, 7>(A, x, pre, f, xs);
       else sell_rows_narrow<false, kSellPair, 7>(A, x, pre, f, xs);
     } else if (nw == 27) {
-      if (A.sell_xcd) sell_rows_narrow<true, 1, 27>(A, x, pre, f, xs);
-      else sell_rows_narrow<false, 1, 27>(A, x, pre, f, xs);
+      if (A.sell_xcd) sell_rows_narrow<true, kSellPair, 27>(A, x, pre, f, xs);
+      else sell_rows_narrow<false, kSellPair, 27>(A, x, pre, f, xs);
     } else if (nw == 5) {
       if (A.sell_xcd) sell_rows_narrow<true, kSellPair, 5>(A, x, pre, f, xs);
       else sell_rows_narrow<false, kSellPair, 5>(A, x, pre, f, xs);
