@@ -553,6 +553,8 @@ def main():
            "mpk_last_gbs": ab3["mpk_last"] / (m3[1] * 1e-3) / 1e9,
            "update_gbs": ab3["update"] / (m3[2] * 1e-3) / 1e9,
            "mpk_mean_launch_ms": m3[0]}
+    big["gram_traffic"] = read_traffic("gram_mfma_3d7_256_chebyshev.txt", sha,
+                                       key="gram_fetch_write_bytes_per_launch")
     # the Chebyshev basis at 256^3: the block Gram pass on the FP64 matrix cores
     cheb_gram = {}
     for sc in (4, 8):
@@ -711,6 +713,18 @@ def main():
 
         A2 = H.matrix_csr_from_stencil("3d27", (N2, N2, N2))
         config2["nnz"] = A2.nnz
+        # matrix powers of the 27-point matrix (5.4 GB, streamed from HBM):
+        # per-launch rates over 4 profiled outer iterations
+        x2.zero_()
+        rp = H.solve(A2, b2, x2, s=S, fixed_outer=4, profile=True)
+        mp = np.array(rp.profile["ms"]) / np.maximum(np.array(rp.profile["launches"]), 1)
+        ab2 = algorithmic_bytes(n2, A2.nnz)
+        config2["roofline_mpk"] = {
+            "bound": "hbm", "achieved": ab2["mpk"] / (mp[0] * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": ab2["mpk"] / (mp[0] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "traffic": read_traffic("traffic_csr_3d27_256.txt", kernel_source_sha()),
+            "kernel": "matrix-powers CSR SpMV + Jacobi (power j < s), 27-point 256^3",
+            "bytes_per_launch": ab2["mpk"], "mean_launch_ms": mp[0]}
         run2(A2, s=S, precision="mixed_ir")   # first use builds the FP32 copy
         config2["csr_sstep_fp64"] = run2(A2, s=S)
         config2["csr_sstep_mixed_ir"] = run2(A2, s=S, precision="mixed_ir")
