@@ -444,6 +444,11 @@ int stencil_args(ssp_handle *h, int kind, int nx, int ny, int nz, const double *
   S.fy = FastDiv{ny, 1.0 / ny};
   S.k = nullptr;
   A->n = n;
+  // SSP_MPK_TEMPORAL=0: one launch per matrix power everywhere; =2: the
+  // temporally blocked launches wherever they apply, also on grids too small
+  // to fill the GPU (for comparisons and tests)
+  const char *tb = getenv("SSP_MPK_TEMPORAL");
+  A->tb = (tb && tb[0] == '0') ? 0 : (tb && tb[0] == '2') ? 2 : 1;
   if (kind == SSP_STENCIL_3D7_VARK) {
     if (!coef) return fail(h, SSP_EINVAL, "3D7_VARK needs the device coefficient array");
     S.k = coef;

@@ -15,6 +15,7 @@
 
 #include "gram.hpp"
 #include "kernels.hpp"
+#include "temporal.hpp"
 #include "sstep.h"
 
 namespace ssp {
@@ -91,6 +92,8 @@ struct ssp_matrix {
   double dconst = 1.0;             // Jacobi constant (constant-diagonal stencils)
   bool has32 = false;
   int prec = SSP_PREC_JACOBI;
+  int tb = 1;                      // temporally blocked powers: 0 never, 1 where they
+                                   // fill the GPU, 2 wherever they apply
 };
 
 namespace ssp {
@@ -275,6 +278,66 @@ struct IterBufs {
   double cheb_c = 0.0, cheb_g = 0.0;   // Chebyshev basis: centre, 1 / half-width
 };
 
+// The temporally blocked powers apply to the 3D 7-point constant-coefficient
+// grid (whose Jacobi factor is a constant) for s >= 2, when a plane of
+// 32 x 32 tiles fits one launch.  By default they are taken only where their
+// launches keep at least three quarters of the compute units busy (on
+// smaller grids one launch per power is faster: 64^3 s = 4 2.8 vs 4.9 ms);
+// tb = 2 takes them wherever they apply, tb = 0 never.
+inline bool tb_usable(const ssp_matrix *A, int s) {
+  if (A->kind != SSP_STENCIL_3D7 || s < 2 || A->tb == 0) return false;
+  const StencilArgs<double> &S = A->sten;
+  const int64_t plane = (int64_t)((S.nx + kTbT - 1) / kTbT) * ((S.ny + kTbT - 1) / kTbT);
+  if (plane > kGridMax) return false;
+  if (A->tb == 2) return true;
+  const int L = s < kTbMaxL ? s : kTbMaxL;
+  return tb_grid(tb_tiling(S.nx, S.ny, S.nz, L, 1)) * 4 >= 3 * kCUs;
+}
+
+// Workgroups of a blocked-powers kernel resident per compute unit (its
+// registers and LDS decide), asked of the runtime once.
+template <int L, int SM, typename T>
+int tb_per_cu() {
+  static int n = -1;
+  if (n < 0) {
+    int v = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_mpk_tb7<L, SM, T>, kTbWG, 0) !=
+        hipSuccess)
+      v = 1;
+    n = std::max(v, 1);
+  }
+  return n;
+}
+
+// Launch PASS of the temporally blocked powers of an S-power block and the
+// launches after it; G is set to the grid of the last (the one leaving the
+// moment partials).
+template <int S, int PASS, typename T>
+void tb_pass(ssp_handle *h, const ssp_matrix *A, const T *in, const T *r, T c, int j0, T *P,
+             int64_t ld, bool store_z, DevState *st, double *partials, int &G) {
+  constexpr int L = tb_levels(S, PASS);
+  constexpr bool last = PASS == tb_passes(S) - 1;
+  T *tag = nullptr;
+  const StencilArgs<T> &sa = sten_of(A, tag);
+  const TbTiling tl = tb_tiling(sa.nx, sa.ny, sa.nz, L, tb_per_cu<L, last ? S : 0, T>());
+  G = tl.ntx * tl.nty * tl.ntz;
+  k_mpk_tb7<L, last ? S : 0, T><<<G, kTbWG, 0, h->stream>>>(
+      sa, in, c, j0, S, P, ld, store_z ? 1 : 0, r, st, partials, tl);
+  if constexpr (!last)
+    tb_pass<S, PASS + 1, T>(h, A, P + (int64_t)(S + j0 + L - 1) * ld, r, c, j0 + L, P, ld,
+                            store_z, st, partials, G);
+}
+
+// AZ(:,1..S) of the block P (and Z(:,2..S) when store_z) from r, with the
+// moment partials of Alg. 5 in `partials` (G workgroups).
+template <int S, typename T>
+int tb_powers(ssp_handle *h, const ssp_matrix *A, const T *r, T c, T *P, int64_t ld,
+              bool store_z, DevState *st, double *partials, int &G) {
+  tb_pass<S, 0, T>(h, A, r, r, c, 0, P, ld, store_z, st, partials, G);
+  LAUNCHCHK(h);
+  return SSP_OK;
+}
+
 // One outer iteration of the s-step method (Alg. 3): s matrix-power
 // launches (Alg. 4; the last fused with Alg. 5 and followed by the s x s
 // solve of Alg. 6 on the GPU) and the fused block update.  Within a batch of
@@ -294,7 +357,28 @@ int sstep_iteration(ssp_handle *h, const ssp_matrix *A, const IterBufs<T> &B, in
   // constant Jacobi scaling c (or none, c = 1): the Z columns are never
   // stored; each reader forms c * r or c * AZ(:,j-1), the same rounded values
   const T zc = pc.dinv ? T(0) : pc.dc;
-  for (int j = 1; j <= S; ++j) {
+  bool powers_done = false;
+  if constexpr (S >= 2) {
+    if (zc != T(0) && tb_usable(A, S)) {
+      // the s powers in ceil(s / 4) temporally blocked launches, then the
+      // moments' reduction and the s x s solve
+      int G = 0;
+      prof_begin(h, 0);
+      int rc = tb_powers<S, T>(h, A, B.r, zc, Pc, B.ld, false, h->st, h->ws.partials, G);
+      prof_end(h);
+      if (rc) return rc;
+      prof_begin(h, 1);
+      k_finalize<EpiMpkLast<S, T>><<<1, kWG, 0, h->stream>>>(
+          EpiMpkLast<S, T>{Pc + (int64_t)(2 * S - 1) * B.ld, Pc, B.ld, B.r, 1, zc,
+                           first_in_batch ? nullptr : h->ws.partials_rr, grid_rows(A->n),
+                           h->ws.hist},
+          h->st, h->ws.partials, G);
+      prof_end(h);
+      LAUNCHCHK(h);
+      powers_done = true;
+    }
+  }
+  for (int j = 1; j <= S && !powers_done; ++j) {
     const T *zin;
     T xs = T(1);
     if (zc == T(0)) {
@@ -393,6 +477,18 @@ int mpk_only(ssp_handle *h, const ssp_matrix *A, const double *r, double *P, int
   const int G = grid_rows(A->n);
   k_prec<double><<<G, kWG, 0, h->stream>>>(A->n, r, P, pc);
   LAUNCHCHK(h);
+  if constexpr (S >= 2) {
+    if (!ctl && !pc.dinv && tb_usable(A, S)) {
+      int Gt = 0;
+      int rc = tb_powers<S, double>(h, A, r, pc.dc, P, ld, true, h->st, h->ws.partials, Gt);
+      if (rc) return rc;
+      k_finalize<EpiMpkLast<S, double>><<<1, kWG, 0, h->stream>>>(
+          EpiMpkLast<S, double>{P + (int64_t)(2 * S - 1) * ld, P, ld, r, 0}, h->st,
+          h->ws.partials, Gt);
+      LAUNCHCHK(h);
+      return SSP_OK;
+    }
+  }
   for (int j = 1; j <= S; ++j) {
     const double *zin = P + (int64_t)(j - 1) * ld;
     double *az = P + (int64_t)(S + j - 1) * ld;
