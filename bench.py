@@ -210,6 +210,9 @@ def bench_batch(H, count=32, lo=32, hi=160, seed=0):
     forms = {}
     for name, tn in (("persistent", sstep.Tune(tile_rows=tune.tile_rows, grid=tune.grid or 1024,
                                                order=tune.order, schedule=0)),
+                     ("persistent_run4", sstep.Tune(tile_rows=tune.tile_rows,
+                                                    grid=tune.grid or 1024, order=tune.order,
+                                                    schedule=0, run=4)),
                      ("stepped", sstep.Tune(tile_rows=tune.tile_rows, schedule=1))):
         ts = []
         for _ in range(3):

@@ -299,6 +299,9 @@ typedef struct ssp_tune {
                           systems together (no in-kernel synchronisation;
                           grid, order and spin_limit unused).  Both give the
                           same results bit for bit                             */
+  int run;             /* persistent schedule: tiles a workgroup claims at once
+                          (one acquire and one release fence per run instead
+                          of per tile); 0 = 1                                  */
 } ssp_tune;
 
 /* Solves nsys independent systems A[i] x[i] = b[i] in ONE persistent launch

@@ -21,9 +21,11 @@ size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 template <int... Ss>
 struct BatchTable {
   static int launch(int s, int grid, hipStream_t st, const BatchSys *sys, BatchSched *sched,
-                    BatchGlobal *glob, int nsys, const int *order_arr, int order, unsigned spin) {
+                    BatchGlobal *glob, int nsys, const int *order_arr, int order, unsigned spin,
+                    int run) {
     int done = 0;
-    ((s == Ss ? (k_batch<Ss><<<grid, kWG, 0, st>>>(sys, sched, glob, nsys, order_arr, order, spin),
+    ((s == Ss ? (k_batch<Ss><<<grid, kWG, 0, st>>>(sys, sched, glob, nsys, order_arr, order, spin,
+                                                    run),
                  done = 1, 0)
               : 0),
      ...);
@@ -81,6 +83,8 @@ int ssp_solve_batch(ssp_handle *h, int nsys, const ssp_matrix *const *A, const d
   const unsigned spin = (tune && tune->spin_limit > 0) ? (unsigned)tune->spin_limit : kDefaultSpin;
   const int64_t trq = tune ? tune->tile_rows : 0;
   const int schedule = tune ? tune->schedule : 0;
+  const int run = (tune && tune->run > 0) ? tune->run : 1;
+  if (run > (1 << 20)) return fail(h, SSP_EINVAL, "ssp_solve_batch: run must be <= 2^20");
   if (schedule != 0 && schedule != 1) return fail(h, SSP_EINVAL, "ssp_solve_batch: bad schedule");
 
   // layout of the per-system arrays in one device buffer
@@ -207,7 +211,7 @@ int ssp_solve_batch(ssp_handle *h, int nsys, const ssp_matrix *const *A, const d
   if (schedule == 0) {
     if (!BT::launch(s, grid, h->stream, (const BatchSys *)(base + off_sys),
                     (BatchSched *)(base + off_sched), (BatchGlobal *)(base + off_glob), nsys,
-                    (const int *)(base + off_order), order, spin))
+                    (const int *)(base + off_order), order, spin, run))
       return fail(h, SSP_EINVAL, "ssp_solve_batch: no kernel for s");
     LAUNCHCHK(h);
   } else {
@@ -298,12 +302,13 @@ int ssp_autotune_batch(ssp_handle *h, int nsys, const ssp_matrix *const *A,
       if (line.rfind(key.str() + " ", 0) == 0) {
         std::istringstream f(line.substr(key.str().size()));
         std::string tag;
-        ssp_tune t{0, 0, 0, 0, 0};
+        ssp_tune t{0, 0, 0, 0, 0, 0};
         while (f >> tag) {
           if (tag.rfind("tile_rows=", 0) == 0) t.tile_rows = std::stoi(tag.substr(10));
           else if (tag.rfind("grid=", 0) == 0) t.grid = std::stoi(tag.substr(5));
           else if (tag.rfind("order=", 0) == 0) t.order = std::stoi(tag.substr(6));
           else if (tag.rfind("schedule=", 0) == 0) t.schedule = std::stoi(tag.substr(9));
+          else if (tag.rfind("run=", 0) == 0) t.run = std::stoi(tag.substr(4));
         }
         if (t.grid > 0 || t.schedule == 1) {
           *out = t;
@@ -331,7 +336,7 @@ int ssp_autotune_batch(ssp_handle *h, int nsys, const ssp_matrix *const *A,
   const int tiles[] = {0, 16384, 65536, 262144};
   const int grids[] = {256, 512, 1024, 2048};
   double best = 1e300;
-  ssp_tune bt{0, 512, 0, 0, 0};
+  ssp_tune bt{0, 512, 0, 0, 0, 0};
   int rc = SSP_OK;
   auto trial = [&](const ssp_tune &t) {
     double ms = 0.0;
@@ -349,19 +354,33 @@ int ssp_autotune_batch(ssp_handle *h, int nsys, const ssp_matrix *const *A,
       best = ms;
       bt = t;
     }
+    return rc >= 0 ? ms : 1e300;
   };
+  ssp_tune bp{0, 512, 0, 0, 0, 0};   // the best persistent candidate
+  double bp_ms = 1e300;
   for (int ti : tiles) {
     for (int gi : grids)
-      for (int oi = 0; oi < 2 && rc >= 0; ++oi) trial(ssp_tune{ti, gi, oi, 0, 0});
-    if (rc >= 0) trial(ssp_tune{ti, 0, 0, 0, 1});
+      for (int oi = 0; oi < 2 && rc >= 0; ++oi) {
+        const ssp_tune t{ti, gi, oi, 0, 0, 0};
+        const double ms = trial(t);
+        if (ms < bp_ms) {
+          bp = t;
+          bp_ms = ms;
+        }
+      }
+    if (rc >= 0) trial(ssp_tune{ti, 0, 0, 0, 1, 0});
   }
+  // then the best persistent candidate with longer runs of tiles per claim
+  for (int ru : {2, 4, 8, 16})
+    if (rc >= 0) trial(ssp_tune{bp.tile_rows, bp.grid, bp.order, 0, 0, ru});
   for (double *p : xs) (void)hipFree(p);
   if (rc < 0) return rc;
   *out = bt;
   if (cache_path) {
     std::ofstream f(cache_path, std::ios::app);
     f << key.str() << " tile_rows=" << bt.tile_rows << " grid=" << bt.grid
-      << " order=" << bt.order << " schedule=" << bt.schedule << " ms=" << best << "\n";
+      << " order=" << bt.order << " schedule=" << bt.schedule << " run=" << bt.run
+      << " ms=" << best << "\n";
   }
   return SSP_OK;
 }

@@ -9,10 +9,11 @@
 //   IRADD  (tiles) x += d                                        -> RESID
 //   DONE
 //
-// A phase is split into tiles of rows.  Persistent workgroups claim tiles
-// from any system with unclaimed work (a 64-bit word per system packs the
-// phase sequence number and the next tile, so a claim can never be applied
-// to the wrong phase), process them, and count them done.  The workgroup that
+// A phase is split into tiles of rows.  Persistent workgroups claim runs of
+// up to `run` consecutive tiles from any system with unclaimed work (a 64-bit
+// word per system packs the phase sequence number and the next tile, so a
+// claim can never be applied to the wrong phase), process them, and count
+// them done.  The workgroup that
 // completes a phase's last tile reduces the phase's partial sums, runs the
 // finishing step (stopping tests, the s x s solve) and publishes the next
 // phase.  No workgroup ever waits for another: an idle workgroup polls the
@@ -22,7 +23,8 @@
 // Memory ordering: tile outputs are released (agent-scope release fence in
 // every wave, then the done counter increment); the finishing workgroup and
 // the claimers of the next phase acquire (agent-scope acquire fence after the
-// atomic) before reading them.
+// atomic) before reading them.  On gfx950 these fences write back and
+// invalidate the XCD's L2, so they are taken once per run of tiles.
 #pragma once
 
 #include "kernels.hpp"
@@ -206,8 +208,8 @@ template <int S>
 __global__ __launch_bounds__(kWG) void k_batch(const BatchSys *__restrict__ sys,
                                                BatchSched *sched, BatchGlobal *glob, int nsys,
                                                const int *__restrict__ scan_order, int order,
-                                               unsigned spin_limit) {
-  __shared__ int s_sys, s_tile, s_exit;
+                                               unsigned spin_limit, int run) {
+  __shared__ int s_sys, s_tile, s_cnt, s_exit;
   unsigned idle = 0, last_progress = 0;
   const int start = (order == 1) ? (int)(blockIdx.x % (unsigned)nsys) : 0;
   for (;;) {
@@ -225,12 +227,13 @@ __global__ __launch_bounds__(kWG) void k_batch(const BatchSys *__restrict__ sys,
           const unsigned long long c =
               __hip_atomic_load(&sc->claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           if ((unsigned)(c & 0xffffffffull) >= (unsigned)sys[i].ntiles) continue;
-          const unsigned long long c2 = __hip_atomic_fetch_add(&sc->claim, 1ull, __ATOMIC_RELAXED,
-                                                               __HIP_MEMORY_SCOPE_AGENT);
+          const unsigned long long c2 = __hip_atomic_fetch_add(
+              &sc->claim, (unsigned long long)run, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           const unsigned t = (unsigned)(c2 & 0xffffffffull);
           if (t < (unsigned)sys[i].ntiles) {
             s_sys = i;
             s_tile = (int)t;
+            s_cnt = (int)min((unsigned)run, (unsigned)sys[i].ntiles - t);
           }
         }
         if (s_sys < 0) {
@@ -258,15 +261,16 @@ __global__ __launch_bounds__(kWG) void k_batch(const BatchSys *__restrict__ sys,
     BatchSched sc;
     sc.phase = __hip_atomic_load(&sched[i].phase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     sc.j = __hip_atomic_load(&sched[i].j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    batch_tile<S>(y, sc, s_tile);
+    const int cnt = s_cnt;
+    for (int k = 0; k < cnt; ++k) batch_tile<S>(y, sc, s_tile + k);
     fence_release();
     __syncthreads();
     __shared__ int s_last;
     if (threadIdx.x == 0) {
-      const unsigned d = __hip_atomic_fetch_add(&sched[i].done, 1u, __ATOMIC_RELAXED,
+      const unsigned d = __hip_atomic_fetch_add(&sched[i].done, (unsigned)cnt, __ATOMIC_RELAXED,
                                                 __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_fetch_add(&glob->progress, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      s_last = (d + 1 == (unsigned)y.ntiles);
+      s_last = (d + (unsigned)cnt == (unsigned)y.ntiles);
     }
     __syncthreads();
     if (!s_last) continue;

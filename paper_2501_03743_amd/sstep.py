@@ -54,9 +54,9 @@ class SspError(RuntimeError):
 
 class Tune(C.Structure):
     """Batched-solver tuning (ssp_tune): tile_rows, grid, order, spin_limit,
-    schedule (0 persistent launch, 1 stepped)."""
+    schedule (0 persistent launch, 1 stepped), run (tiles per claim)."""
     _fields_ = [("tile_rows", C.c_int), ("grid", C.c_int), ("order", C.c_int),
-                ("spin_limit", C.c_int), ("schedule", C.c_int)]
+                ("spin_limit", C.c_int), ("schedule", C.c_int), ("run", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -134,23 +134,26 @@ def test_autotune_and_cache(H, tmp_path):
 
 @pytest.mark.parametrize("tile_rows", [0, 4096])
 def test_stepped_schedule_equals_persistent_bitwise(H, tile_rows):
-    """The stepped schedule (one launch pair per phase step) runs each tile's
-    arithmetic exactly as the persistent kernel does: same results bit for
-    bit, for uneven systems that finish at different steps."""
+    """The stepped schedule (one launch pair per phase step) and the
+    persistent kernel claiming one tile or runs of 3 or 8 tiles at a time run
+    each tile's arithmetic identically: same results bit for bit, for uneven
+    systems that finish at different steps."""
     from paper_2501_03743_amd import sstep
     sides = [28, 9, 45, 17, 33, 6]
     mats, ks, bs, keep = _systems(H, sides, seed0=500)
     out = {}
-    for sched in (0, 1):
+    for sched, run in ((0, 1), (1, 0), (0, 3), (0, 8)):
         xs = [torch.zeros_like(b) for b in bs]
-        tune = sstep.Tune(tile_rows=tile_rows, grid=256, order=0, schedule=sched)
+        tune = sstep.Tune(tile_rows=tile_rows, grid=256, order=0, schedule=sched, run=run)
         rc, st, it, tr = H.solve_batch(mats, bs, xs, s=4, rtol=1e-9, tune=tune)
-        assert rc == 0 and (st == 0).all(), (sched, st)
-        out[sched] = (xs, it.copy(), tr.copy())
-    for i in range(len(sides)):
-        assert torch.equal(out[0][0][i], out[1][0][i]), i
-    assert (out[0][1] == out[1][1]).all()
-    assert np.array_equal(out[0][2], out[1][2])
+        assert rc == 0 and (st == 0).all(), (sched, run, st)
+        out[(sched, run)] = (xs, it.copy(), tr.copy())
+    for key in ((0, 1), (0, 3), (0, 8)):
+        for i in range(len(sides)):
+            assert torch.equal(out[key][0][i], out[(1, 0)][0][i]), (key, i)
+        assert (out[key][1] == out[(1, 0)][1]).all(), key
+        assert np.array_equal(out[key][2], out[(1, 0)][2]), key
+    out[1] = out[(1, 0)]
     if tile_rows == 0:
         for i, (M, b) in enumerate(zip(mats, bs)):
             x1 = torch.zeros_like(b)
