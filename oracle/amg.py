@@ -9,12 +9,17 @@ of a hierarchy of coarser matrices built from A.  The paper refers to its
 library for the details; this oracle takes a standard reading, the smoothed
 aggregation of Vanek, Mandel and Brezina (1996), written out plainly:
 
-* strength: j != i is a strong neighbour of i when a_ij^2 >= theta^2 |a_ii a_jj|;
+* strength: j != i is a strong neighbour of i when a_ij^2 >= theta_l^2 |a_ii a_jj|,
+  theta_l = theta 2^-l on level l (the coarse operators' couplings are
+  weaker relative to their diagonals; with a fixed theta the 3D hierarchy
+  stalls after one level);
 * aggregation in three passes over the rows in index order: (1) a row whose
   strong neighbours are all free starts an aggregate with them; (2) a row
   still free joins the pass-1 aggregate of its strongest aggregated strong
-  neighbour (ties: the smallest column); (3) a row still free starts an
-  aggregate with its free strong neighbours;
+  neighbour (weights within a relative 1e-9 count as ties, won by the
+  smallest column, so that rounding in the Galerkin sums of a coarse level
+  cannot decide the choice); (3) a row still free starts an aggregate with
+  its free strong neighbours;
 * tentative prolongator P_t(i, agg(i)) = 1, smoothed
   P = (I - omega_p D^-1 A) P_t with omega_p = 4 / (3 rho_G), rho_G the
   Gershgorin bound max_i sum_j |a_ij| / |a_ii| of rho(D^-1 A);
@@ -39,6 +44,7 @@ OMEGA = 2.0 / 3.0
 NU = 1
 MAX_COARSE = 64
 MAX_LEVELS = 10
+TIE = 1e-9          # relative width of a tie between neighbour weights
 
 
 def strength(A: sp.csr_matrix, theta: float = THETA):
@@ -80,7 +86,9 @@ def aggregate(A: sp.csr_matrix, theta: float = THETA):
             continue
         best, bw = -1, -1.0
         for j, w in S[i]:
-            if first[j] >= 0 and (w > bw or (w == bw and j < best)):
+            if first[j] < 0:
+                continue
+            if best < 0 or w > bw * (1.0 + TIE) or (w >= bw * (1.0 - TIE) and j < best):
                 best, bw = j, w
         if best >= 0:
             agg[i] = first[best]
@@ -125,7 +133,7 @@ class Hierarchy:
         self.A, self.P, self.R, self.aggs = [A], [], [], []
         while (self.A[-1].shape[0] > max_coarse and len(self.A) < max_levels):
             Al = self.A[-1]
-            agg, nc = aggregate(Al, theta)
+            agg, nc = aggregate(Al, theta * 0.5 ** (len(self.A) - 1))
             if nc >= 0.9 * Al.shape[0] or nc == 0:
                 break
             P = prolongator(Al, agg, nc)
