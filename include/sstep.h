@@ -68,6 +68,8 @@ typedef struct ssp_matrix ssp_matrix;
 #define SSP_PREC_NONE 0       /* B = I (Sec. V-A "no preconditioning")          */
 #define SSP_PREC_JACOBI 1     /* B = diag(A) (the weighted-Jacobi building block
                                  of the paper's AMG smoother, Sec. III-A)       */
+#define SSP_PREC_AMG 2        /* B^-1 = one V-cycle of the aggregation AMG that
+                                 ssp_set_amg builds (Sec. III-A)                */
 
 /* ---- solver options ------------------------------------------------------ */
 #define SSP_METHOD_SSTEP 0    /* Alg. 3 with Alg. 4-6                           */
@@ -191,8 +193,49 @@ int ssp_matrix_csr_form(const ssp_matrix *A, int *form);
 
 int ssp_matrix_destroy(ssp_matrix *A);
 
-/* SSP_PREC_NONE or SSP_PREC_JACOBI. */
+/* SSP_PREC_NONE, SSP_PREC_JACOBI, or SSP_PREC_AMG once ssp_set_amg has built
+ * the matrix's hierarchy (SSP_EINVAL otherwise). */
 int ssp_set_preconditioner(ssp_matrix *A, int kind);
+
+/* ---- AMG preconditioner -------------------------------------------------- */
+
+/* The paper's weak-scaling preconditioner (Sec. III-A, Sec. V-B) is an
+ * algebraic multigrid whose B^-1 is weighted-Jacobi sweeps on each level of a
+ * hierarchy of coarser matrices built from A.  This one is smoothed
+ * aggregation: strength a_ij^2 >= theta^2 |a_ii a_jj|; three-pass greedy
+ * aggregation in row order; P = (I - 4/(3 rho_G) D^-1 A) P_t with rho_G the
+ * Gershgorin bound of rho(D^-1 A); A_c = P^T A P, R = P^T; the coarsest level
+ * is solved with its dense inverse.  B^-1 y is one V-cycle: `sweeps` Jacobi
+ * sweeps with weight omega before (the first from zero) and after the coarse
+ * correction, so B^-1 is symmetric.  The strength threshold halves from one
+ * level to the next (theta 2^-l on level l).  All fields 0 = default. */
+#define SSP_AMG_MAX_LEVELS 16
+#define SSP_AMG_DENSE_MAX 4096   /* rows of the coarsest level at most */
+typedef struct ssp_amg_opts {
+  double theta;     /* strength threshold of level 0 (default 0.08)             */
+  double omega;     /* Jacobi weight of the smoother (default 2/3)              */
+  int sweeps;       /* sweeps before and after the coarse correction (1)        */
+  int max_coarse;   /* coarsening stops at this many rows (64)                  */
+  int max_levels;   /* at most this many levels (10)                            */
+} ssp_amg_opts;
+
+/* Builds A's hierarchy (on the host, once; the level matrices, prolongators,
+ * restrictions and the coarse inverse then live on the device with the
+ * matrix) and makes SSP_PREC_AMG A's preconditioner.  CSR matrices with a
+ * positive diagonal only (SSP_EUNSUPPORTED for grid operators: build their
+ * CSR form with ssp_matrix_csr_from_stencil).  SSP_EUNSUPPORTED also when the
+ * coarsest level would exceed SSP_AMG_DENSE_MAX rows.  The s-step method
+ * (FP64, monomial basis) and ssp_mpk use it; other methods and precisions
+ * return SSP_EUNSUPPORTED with it.  A later call rebuilds the hierarchy. */
+int ssp_set_amg(ssp_handle *h, ssp_matrix *A, const ssp_amg_opts *opts);
+
+/* Number of levels of A's hierarchy (0: none) and, if rows is not NULL, the
+ * rows of each level (HOST array of at least SSP_AMG_MAX_LEVELS entries). */
+int ssp_amg_levels(const ssp_matrix *A, int *levels, int64_t *rows);
+
+/* z = B^-1 y: one V-cycle (DEVICE vectors of length n, distinct), enqueued on
+ * the handle's stream. */
+int ssp_amg_apply(ssp_handle *h, const ssp_matrix *A, const double *y, double *z);
 
 /* ---- building blocks ------------------------------------------------------- */
 

@@ -16,9 +16,9 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libsstep.so")
-SOURCES = ["capi.hip", "inst_f64.hip", "inst_f32.hip", "batch.hip", "unet.hip"]
+SOURCES = ["capi.hip", "inst_f64.hip", "inst_f32.hip", "batch.hip", "unet.hip", "amg.hip"]
 HEADERS = ["common.hpp", "operators.hpp", "small_solve.hpp", "kernels.hpp", "gram.hpp", "measure.hpp",
-           "setup_kernels.hpp", "engine.hpp", "batch.hpp"]
+           "setup_kernels.hpp", "engine.hpp", "batch.hpp", "temporal.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

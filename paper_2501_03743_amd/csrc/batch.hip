@@ -73,6 +73,8 @@ int ssp_solve_batch(ssp_handle *h, int nsys, const ssp_matrix *const *A, const d
     if (!A[i] || A[i]->h != h || !b[i] || !x[i])
       return fail(h, SSP_EINVAL, "ssp_solve_batch: system " + std::to_string(i) + " is invalid");
     if (s > A[i]->n) return fail(h, SSP_EINVAL, "ssp_solve_batch: s exceeds a system size");
+    if (A[i]->prec == SSP_PREC_AMG)
+      return fail(h, SSP_EUNSUPPORTED, "ssp_solve_batch: the AMG preconditioner is not batched");
   }
   HIPCHK(h, hipSetDevice(h->device));
   const double inner_rtol = (opts && opts->inner_rtol > 0.0) ? opts->inner_rtol : 1e-5;

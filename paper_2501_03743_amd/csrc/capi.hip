@@ -565,6 +565,10 @@ int solve_sstep(ssp_handle *h, const ssp_matrix *A, const double *b, double *x, 
   // r = b - A x0 and z1 = B^-1 r into column 1 of the block used at k = 0
   rc = launch_op<double>(h, A, x, EpiInit{b, w.r, w.P2, prec_of(A, tag), w.hist}, 3);
   if (rc) return rc;
+  if (A->prec == SSP_PREC_AMG) {   // z1 = B^-1 r by a V-cycle
+    rc = amg_vcycle(h, A, w.r, w.P2);
+    if (rc) return rc;
+  }
   const iter_fn<double> step = cheb ? cheb_iteration_f64(s) : iteration_f64(s);
   const IterBufs<double> B{w.P1, w.P2, w.ld, x, w.r, cc, cg};
   const int trace_cap = (o && o->trace_cap > 0 && o->trace_vm && o->trace_alpha &&
@@ -1075,12 +1079,15 @@ int ssp_matrix_destroy(ssp_matrix *A) {
   hfree_t(A->k32);
   hfree_t(A->dinv);
   hfree_t(A->dinv32);
+  amg_free(A);
   delete A;
   return SSP_OK;
 }
 
 int ssp_set_preconditioner(ssp_matrix *A, int kind) {
-  if (!A || (kind != SSP_PREC_NONE && kind != SSP_PREC_JACOBI)) return SSP_EINVAL;
+  if (!A || (kind != SSP_PREC_NONE && kind != SSP_PREC_JACOBI && kind != SSP_PREC_AMG))
+    return SSP_EINVAL;
+  if (kind == SSP_PREC_AMG && !A->amg) return SSP_EINVAL;
   A->prec = kind;
   return SSP_OK;
 }
@@ -1207,6 +1214,12 @@ int ssp_solve(ssp_handle *h, const ssp_matrix *A, const double *b, double *x, in
     return fail(h, SSP_EINVAL, "ssp_solve: unknown basis " + std::to_string(basis));
   if (basis == SSP_BASIS_CHEBYSHEV && method != SSP_METHOD_SSTEP)
     return fail(h, SSP_EUNSUPPORTED, "ssp_solve: the Chebyshev basis is for the s-step method");
+  if (A->prec == SSP_PREC_AMG &&
+      (method != SSP_METHOD_SSTEP || precision != SSP_PRECISION_FP64 ||
+       basis != SSP_BASIS_MONOMIAL || (opts && opts->warm_start)))
+    return fail(h, SSP_EUNSUPPORTED,
+                "ssp_solve: the AMG preconditioner runs with the FP64 s-step method on the "
+                "monomial basis without a warm start");
   HIPCHK(h, hipSetDevice(h->device));
   h->prof_on = opts && opts->profile;
   h->ev_used = 0;

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "gram.hpp"
@@ -69,6 +70,10 @@ struct ssp_handle {
   size_t batch_bytes = 0;
 };
 
+namespace ssp {
+struct AmgHier;
+}
+
 struct ssp_matrix {
   ssp_handle *h = nullptr;
   int kind = 0;                    // 0 = CSR, else SSP_STENCIL_*
@@ -92,6 +97,7 @@ struct ssp_matrix {
   double dconst = 1.0;             // Jacobi constant (constant-diagonal stencils)
   bool has32 = false;
   int prec = SSP_PREC_JACOBI;
+  ssp::AmgHier *amg = nullptr;     // AMG hierarchy (ssp_set_amg)
   int tb = 1;                      // temporally blocked powers: 0 never, 1 where they
                                    // fill the GPU, 2 wherever they apply
 };
@@ -115,13 +121,19 @@ inline int fail(ssp_handle *h, int code, const std::string &msg) {
 
 template <typename T> struct Prec;
 
+// z = B^-1 y by one AMG V-cycle (amg.hip); and the hierarchy's release.
+int amg_vcycle(ssp_handle *h, const ssp_matrix *A, const double *y, double *z);
+void amg_free(ssp_matrix *A);
+
+// The pointwise preconditioner of the fused epilogues.  With the AMG
+// preconditioner they apply the identity and a V-cycle runs after them.
 inline Prec<double> prec_of(const ssp_matrix *A, double *) {
-  if (A->prec == SSP_PREC_NONE) return Prec<double>{nullptr, 1.0};
+  if (A->prec == SSP_PREC_NONE || A->prec == SSP_PREC_AMG) return Prec<double>{nullptr, 1.0};
   if (A->dinv) return Prec<double>{A->dinv, 0.0};
   return Prec<double>{nullptr, A->dconst};
 }
 inline Prec<float> prec_of(const ssp_matrix *A, float *) {
-  if (A->prec == SSP_PREC_NONE) return Prec<float>{nullptr, 1.0f};
+  if (A->prec == SSP_PREC_NONE || A->prec == SSP_PREC_AMG) return Prec<float>{nullptr, 1.0f};
   if (A->dinv32) return Prec<float>{A->dinv32, 0.0f};
   return Prec<float>{nullptr, (float)A->dconst};
 }
@@ -356,7 +368,11 @@ int sstep_iteration(ssp_handle *h, const ssp_matrix *A, const IterBufs<T> &B, in
   const Prec<T> pc = prec_of(A, tag);
   // constant Jacobi scaling c (or none, c = 1): the Z columns are never
   // stored; each reader forms c * r or c * AZ(:,j-1), the same rounded values
-  const T zc = pc.dinv ? T(0) : pc.dc;
+  // with AMG the block Z is stored and each Z(:,j+1) = B^-1 AZ(:,j) is a
+  // V-cycle after the power that produced AZ(:,j)
+  constexpr bool kF64 = std::is_same<T, double>::value;
+  const bool amg = kF64 && A->prec == SSP_PREC_AMG;
+  const T zc = (pc.dinv || amg) ? T(0) : pc.dc;
   bool powers_done = false;
   if constexpr (S >= 2) {
     if (zc != T(0) && tb_usable(A, S)) {
@@ -389,10 +405,13 @@ int sstep_iteration(ssp_handle *h, const ssp_matrix *A, const IterBufs<T> &B, in
     }
     T *az = Pc + (int64_t)(S + j - 1) * B.ld;
     int rc;
-    if (j < S)
-      rc = launch_op<T>(h, A, zin,
-                        EpiMpk<T>{az, zc == T(0) ? Pc + (int64_t)j * B.ld : nullptr, pc}, 0, xs);
-    else
+    if (j < S) {
+      rc = launch_op<T>(
+          h, A, zin, EpiMpk<T>{az, (zc == T(0) && !amg) ? Pc + (int64_t)j * B.ld : nullptr, pc},
+          0, xs);
+      if constexpr (kF64)
+        if (!rc && amg) rc = amg_vcycle(h, A, az, Pc + (int64_t)j * B.ld);
+    } else
       rc = launch_op<T>(h, A, zin,
                         EpiMpkLast<S, T>{az, Pc, B.ld, B.r, 1, zc,
                                          first_in_batch ? nullptr : h->ws.partials_rr,
@@ -404,6 +423,12 @@ int sstep_iteration(ssp_handle *h, const ssp_matrix *A, const IterBufs<T> &B, in
   prof_begin(h, 2);
   k_update<S, T><<<G, kWG, 0, h->stream>>>(A->n, B.ld, Pc, Po, B.x, B.r, pc, zc, h->st,
                                             h->ws.partials_rr);
+  if constexpr (kF64)
+    if (amg) {   // z_1 = B^-1 r of the next iteration, where the update left r
+      LAUNCHCHK(h);
+      const int rc = amg_vcycle(h, A, B.r, Po);
+      if (rc) return rc;
+    }
   if (last_in_batch)
     k_finalize<FinUpdate><<<1, kWG, 0, h->stream>>>(FinUpdate{h->ws.hist}, h->st,
                                                     h->ws.partials_rr, G);
@@ -475,10 +500,17 @@ int mpk_only(ssp_handle *h, const ssp_matrix *A, const double *r, double *P, int
   double *tag = nullptr;
   const Prec<double> pc = prec_of(A, tag);
   const int G = grid_rows(A->n);
-  k_prec<double><<<G, kWG, 0, h->stream>>>(A->n, r, P, pc);
+  const bool amg = A->prec == SSP_PREC_AMG;
+  if (amg) {
+    if (ctl) return fail(h, SSP_EUNSUPPORTED, "the AMG preconditioner allocates no scratch here");
+    int rc = amg_vcycle(h, A, r, P);
+    if (rc) return rc;
+  } else {
+    k_prec<double><<<G, kWG, 0, h->stream>>>(A->n, r, P, pc);
+  }
   LAUNCHCHK(h);
   if constexpr (S >= 2) {
-    if (!ctl && !pc.dinv && tb_usable(A, S)) {
+    if (!ctl && !amg && !pc.dinv && tb_usable(A, S)) {
       int Gt = 0;
       int rc = tb_powers<S, double>(h, A, r, pc.dc, P, ld, true, h->st, h->ws.partials, Gt);
       if (rc) return rc;
@@ -493,9 +525,11 @@ int mpk_only(ssp_handle *h, const ssp_matrix *A, const double *r, double *P, int
     const double *zin = P + (int64_t)(j - 1) * ld;
     double *az = P + (int64_t)(S + j - 1) * ld;
     int rc;
-    if (j < S)
-      rc = launch_op<double>(h, A, zin, EpiMpk<double>{az, P + (int64_t)j * ld, pc}, 0, 1.0, ctl);
-    else
+    if (j < S) {
+      rc = launch_op<double>(h, A, zin, EpiMpk<double>{az, amg ? nullptr : P + (int64_t)j * ld, pc},
+                             0, 1.0, ctl);
+      if (!rc && amg) rc = amg_vcycle(h, A, az, P + (int64_t)j * ld);
+    } else
       rc = launch_op<double>(h, A, zin, EpiMpkLast<S, double>{az, P, ld, r, 0}, 1, 1.0, ctl);
     if (rc) return rc;
   }

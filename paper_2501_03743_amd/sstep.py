@@ -24,7 +24,8 @@ EINVAL, ENOMEM, EHIP, EUNSUPPORTED = -1, -2, -3, -4
 SMAX = 16
 STENCIL = {"2d5": 1, "3d7": 2, "3d27": 3, "3d7_vark": 4}
 BORROW, COPY, VALIDATE = 0, 1, 2
-PREC = {"none": 0, "jacobi": 1}
+PREC = {"none": 0, "jacobi": 1, "amg": 2}
+AMG_MAX_LEVELS = 16
 METHOD = {"sstep": 0, "pcg": 1, "pfcg": 2}
 PRECISION = {"fp64": 0, "mixed_ir": 1}
 BASIS = {"monomial": 0, "chebyshev": 1}
@@ -42,7 +43,7 @@ EXPORTS = (
     "ssp_net_adam_step", "ssp_net_get_state", "ssp_net_set_state", "ssp_conv3d",
     "ssp_conv3d_wgrad", "ssp_net_mfma_selftest", "ssp_get_warm_start", "ssp_get_restarts",
     "ssp_net_loss_h1", "ssp_matrix_csr_form", "ssp_mpk_noalloc", "ssp_cheb_basis",
-    "ssp_stream_probe",
+    "ssp_stream_probe", "ssp_set_amg", "ssp_amg_levels", "ssp_amg_apply",
 )
 
 
@@ -60,6 +61,12 @@ class Tune(C.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class AmgOpts(C.Structure):
+    """AMG hierarchy options (ssp_amg_opts; 0 = default)."""
+    _fields_ = [("theta", C.c_double), ("omega", C.c_double), ("sweeps", C.c_int),
+                ("max_coarse", C.c_int), ("max_levels", C.c_int)]
 
 
 class _Opts(C.Structure):
@@ -136,6 +143,9 @@ def load():
         "ssp_conv3d": (i32, [vp, i32, vp, i32, i32, i32, i32, i32, vp, i32, i32, vp]),
         "ssp_conv3d_wgrad": (i32, [vp, vp, i32, i32, i32, i32, i32, vp, i32, i32, vp, vp]),
         "ssp_net_mfma_selftest": (i32, [vp, vp, vp, vp]),
+        "ssp_set_amg": (i32, [vp, vp, C.POINTER(AmgOpts)]),
+        "ssp_amg_levels": (i32, [vp, C.POINTER(i32), vp]),
+        "ssp_amg_apply": (i32, [vp, vp, vp, vp]),
         "ssp_status_string": (C.c_char_p, [i32]),
         "ssp_last_error": (C.c_char_p, [vp]),
     }
@@ -334,6 +344,35 @@ class Handle:
 
     def matrix_csr_from_stencil(self, kind: str, shape, coef=None, k=None) -> Matrix:
         return self._stencil(load().ssp_matrix_csr_from_stencil, kind, shape, coef, k)
+
+    # ---------------------------------------------------------------- AMG
+    def set_amg(self, A: Matrix, theta: float = 0.0, omega: float = 0.0, sweeps: int = 0,
+                max_coarse: int = 0, max_levels: int = 0):
+        """Builds A's aggregation-AMG hierarchy and makes it A's preconditioner
+        (0 = the library default for each option)."""
+        o = AmgOpts(theta=theta, omega=omega, sweeps=sweeps, max_coarse=max_coarse,
+                    max_levels=max_levels)
+        rc = load().ssp_set_amg(self._h, A._p, C.byref(o))
+        if rc:
+            self._err(rc, "ssp_set_amg")
+
+    def amg_levels(self, A: Matrix):
+        """Rows of each level of A's hierarchy (empty: none)."""
+        lv = C.c_int()
+        rows = np.zeros(AMG_MAX_LEVELS, dtype=np.int64)
+        rc = load().ssp_amg_levels(A._p, C.byref(lv), rows.ctypes.data_as(C.c_void_p))
+        if rc:
+            self._err(rc, "ssp_amg_levels")
+        return [int(v) for v in rows[:lv.value]]
+
+    def amg_apply(self, A: Matrix, y, z):
+        """z = B^-1 y (one V-cycle)."""
+        import torch
+        _check_dev(y, torch.float64, A.n, "y")
+        _check_dev(z, torch.float64, A.n, "z")
+        rc = load().ssp_amg_apply(self._h, A._p, _ptr(y), _ptr(z))
+        if rc:
+            self._err(rc, "ssp_amg_apply")
 
     # ---------------------------------------------------------------- building blocks
     def spmv(self, A: Matrix, x, y):
