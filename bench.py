@@ -596,6 +596,25 @@ def main():
         cheb[str(sv)] = row(lambda: solve(s=sv, basis="chebyshev"))
     cheb["8_mixed_ir"] = row(lambda: solve(s=8, basis="chebyshev", precision="mixed_ir"))
     compare["sstep_csr_chebyshev_by_s"] = cheb
+    # the AMG preconditioner (smoothed aggregation; B^-1 = one weighted-Jacobi
+    # V-cycle) on a CSR copy of the same operator; its one-time host setup is
+    # timed on its own and is not part of the solve times
+    Aa = H.matrix_csr_from_stencil("3d7", (N, N, N))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    H.set_amg(Aa)
+    torch.cuda.synchronize()
+    amg_rows = {"setup_s": time.perf_counter() - t0, "levels": H.amg_levels(Aa)}
+
+    def solve_amg(**kw):
+        x.zero_()
+        return H.solve(Aa, b, x, rtol=RTOL, maxit=MAXIT, **kw)
+
+    for sv in (1, 2, 4, 8):
+        amg_rows[str(sv)] = row(lambda: solve_amg(s=sv))
+    compare["sstep_csr_amg_by_s"] = amg_rows
+    Aa.close()
+    log("AMG s=4: %.2f ms, %d outer" % (amg_rows["4"]["tts_s"] * 1e3, amg_rows["4"]["outer"]))
     As = H.matrix_stencil("3d7", (N, N, N))
 
     def solve_st(**kw):
