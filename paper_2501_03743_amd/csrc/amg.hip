@@ -353,12 +353,23 @@ int upload(ssp_handle *h, AmgLevel &L, T *&dst, const T *src, size_t count) {
   return SSP_OK;
 }
 
+// Level matrices run in the LDS-staged CSR form: their rows are long (the
+// Galerkin operators of a 3D hierarchy hold 30-90 entries per row, the
+// restrictions 30-190), which a thread per row would read uncoalesced.
 int upload_csr(ssp_handle *h, AmgLevel &L, CsrArgs<double> &dst, const HostCsr &S) {
   std::vector<int32_t> rp32(S.rp.size());
-  for (size_t i = 0; i < S.rp.size(); ++i) rp32[i] = (int32_t)S.rp[i];
+  int64_t maxrow = 0;
+  for (size_t i = 0; i < S.rp.size(); ++i) {
+    rp32[i] = (int32_t)S.rp[i];
+    if (i > 0) maxrow = std::max<int64_t>(maxrow, S.rp[i] - S.rp[i - 1]);
+  }
   memset(&dst, 0, sizeof(dst));
   dst.n = S.n;
-  dst.variant = CSR_ROW;
+  dst.variant = CSR_STAGED;
+  int64_t R = maxrow > 0 ? kCsrLds / maxrow : kCsrRowsMax;
+  R = std::max<int64_t>(1, std::min<int64_t>(R, kCsrRowsMax));
+  dst.rows_per_rb = (int)R;
+  dst.nrb = (S.n + R - 1) / R;
   int32_t *rp = nullptr, *ci = nullptr;
   double *v = nullptr;
   int rc = upload(h, L, rp, rp32.data(), rp32.size());
@@ -374,8 +385,9 @@ int upload_csr(ssp_handle *h, AmgLevel &L, CsrArgs<double> &dst, const HostCsr &
 // kernels never touch the control block or the partial sums passed to them.
 template <class Epi>
 void level_op(ssp_handle *h, const CsrArgs<double> &M, const double *x, const Epi &epi) {
-  k_csr<CSR_ROW, double, Epi><<<grid_rows(M.n), kWG, 0, h->stream>>>(M, x, 1.0, epi, h->st,
-                                                                       h->ws.partials);
+  const int G = (int)std::max<int64_t>(1, std::min<int64_t>(M.nrb, kGridMax));
+  k_csr<CSR_STAGED, double, Epi><<<G, kWG, 0, h->stream>>>(M, x, 1.0, epi, h->st,
+                                                           h->ws.partials);
 }
 
 // z = B^-1 y on level l (z, y device vectors of the level's size).
@@ -399,29 +411,26 @@ int vcycle(ssp_handle *h, const ssp_matrix *A, AmgHier &H, size_t l, const doubl
     LAUNCHCHK(h);
     return SSP_OK;
   };
-  // the sweeps ping-pong between z and z2 so that the result ends in z
-  k_amg_scale<<<grid_rows(n), kWG, 0, h->stream>>>(n, w, L.dinv, y, z);
+  // each sweep writes the other of the two buffers z, z2; the cycle makes
+  // 2 sweeps - 1 of those swaps, so starting in z2 it ends in z
+  double *buf[2] = {z, L.z2};
+  int cur = 1;
+  k_amg_scale<<<grid_rows(n), kWG, 0, h->stream>>>(n, w, L.dinv, y, buf[cur]);
   LAUNCHCHK(h);
   int rc = SSP_OK;
-  for (int q = 1; q < H.sweeps && !rc; ++q) {
-    rc = op(z, EpiAmgSweep{y, z, L.dinv, w, L.z2});
-    if (!rc) HIPCHK(h, hipMemcpyAsync(z, L.z2, sizeof(double) * n, hipMemcpyDeviceToDevice,
-                                      h->stream));
-  }
-  if (!rc) rc = op(z, EpiAmgResid{y, L.r});
+  for (int q = 1; q < H.sweeps && !rc; ++q, cur ^= 1)
+    rc = op(buf[cur], EpiAmgSweep{y, buf[cur], L.dinv, w, buf[cur ^ 1]});
+  if (!rc) rc = op(buf[cur], EpiAmgResid{y, L.r});
   if (rc) return rc;
   AmgLevel &C = H.lv[l + 1];
   level_op(h, L.R, L.r, EpiStore<double>{C.y});
   LAUNCHCHK(h);
   rc = vcycle(h, A, H, l + 1, C.y, C.z);
   if (rc) return rc;
-  level_op(h, L.P, C.z, EpiAmgAdd{z});
+  level_op(h, L.P, C.z, EpiAmgAdd{buf[cur]});
   LAUNCHCHK(h);
-  for (int q = 0; q < H.sweeps && !rc; ++q) {
-    rc = op(z, EpiAmgSweep{y, z, L.dinv, w, L.z2});
-    if (!rc) HIPCHK(h, hipMemcpyAsync(z, L.z2, sizeof(double) * n, hipMemcpyDeviceToDevice,
-                                      h->stream));
-  }
+  for (int q = 0; q < H.sweeps && !rc; ++q, cur ^= 1)
+    rc = op(buf[cur], EpiAmgSweep{y, buf[cur], L.dinv, w, buf[cur ^ 1]});
   return rc;
 }
 
