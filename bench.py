@@ -428,6 +428,17 @@ def main():
                     help="only this many training steps of the warm-start network at 96^3, "
                          "batch 4 (forward, energy loss, backward, Adam) and as many batch-1 "
                          "forwards: a short target for kernel-trace and MFMA counter runs")
+    ap.add_argument("--stencil-outer", type=int, default=0,
+                    help="only the 3D 7-point matrix-free solve (--stencil-side, s = 4, "
+                         "FP64) for this many outer iterations, with the temporally blocked "
+                         "powers (--stencil-form tb) or one launch per power (per-power): a "
+                         "short target for kernel-trace and counter runs")
+    ap.add_argument("--stencil-side", type=int, default=128)
+    ap.add_argument("--stencil-form", default="tb", choices=("tb", "per-power"))
+    ap.add_argument("--amg-solves", type=int, default=0,
+                    help="only this many AMG-preconditioned s-step solves of the 3D 7-point "
+                         "128^3 CSR system (s = 4, rtol 1e-8): a short target for kernel-trace "
+                         "runs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only the library's plain copy of 1 GiB, three times (the "
                          "reference for the FETCH_SIZE / WRITE_SIZE counter scale)")
@@ -469,6 +480,30 @@ def main():
         print(json.dumps({"workload": "3D 7-point 256^3 CSR", "csr_form": A3.csr_form,
                           "basis": args.csr256_basis, "nnz": A3.nnz, "outer": r3.outer,
                           "profile": r3.profile}))
+        return
+    if args.stencil_outer > 0:
+        Ns = args.stencil_side
+        os.environ["SSP_MPK_TEMPORAL"] = "2" if args.stencil_form == "tb" else "0"
+        As = H.matrix_stencil("3d7", (Ns, Ns, Ns))
+        os.environ.pop("SSP_MPK_TEMPORAL")
+        bs = torch.from_numpy(wl.normal_rhs(Ns ** 3, SEED)).cuda()
+        xs = torch.zeros_like(bs)
+        for _ in range(3):
+            xs.zero_()
+            rs = H.solve(As, bs, xs, s=S, fixed_outer=args.stencil_outer, profile=True)
+        print(json.dumps({"workload": "3D 7-point %d^3 matrix-free" % Ns,
+                          "form": args.stencil_form, "outer": rs.outer, "profile": rs.profile}))
+        return
+    if args.amg_solves > 0:
+        Aa = H.matrix_csr_from_stencil("3d7", (N, N, N))
+        H.set_amg(Aa)
+        ba = torch.from_numpy(wl.normal_rhs(N ** 3, SEED)).cuda()
+        xa = torch.zeros_like(ba)
+        for _ in range(args.amg_solves):
+            xa.zero_()
+            ra = H.solve(Aa, ba, xa, s=S, rtol=RTOL, maxit=MAXIT)
+        print(json.dumps({"workload": "3D 7-point 128^3 CSR, AMG", "levels": H.amg_levels(Aa),
+                          "outer": ra.outer, "true_rel": ra.true_rel}))
         return
     if args.csr27_outer > 0:
         N2 = 256
