@@ -63,7 +63,7 @@ def algorithmic_bytes(n, nnz, s=S):
 def kernel_source_sha():
     h = hashlib.sha256()
     for f in ("common.hpp", "operators.hpp", "kernels.hpp", "small_solve.hpp", "gram.hpp",
-              "engine.hpp", "setup_kernels.hpp", "capi.hip"):
+              "engine.hpp", "setup_kernels.hpp", "capi.hip", "temporal.hpp", "amg.hip"):
         with open(os.path.join(ROOT, "paper_2501_03743_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
