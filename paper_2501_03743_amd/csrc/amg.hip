@@ -318,6 +318,38 @@ bool dense_inverse(const HostCsr &A, std::vector<double> &inv) {
   return true;
 }
 
+// The levels of the hierarchy from the fine matrix F: As[0] = F, then
+// P_l, R_l = P_l^T, A_{l+1} = R_l A_l P_l until a stopping rule holds.
+// Returns false (with the reason) for a non-positive diagonal entry.
+bool build_levels(const HostCsr &F, double theta, int64_t max_coarse, int max_levels,
+                  std::vector<HostCsr> &As, std::vector<HostCsr> &Ps, std::vector<HostCsr> &Rs,
+                  std::vector<std::vector<int64_t>> &aggs, std::string &err) {
+  As.assign(1, F);
+  Ps.clear();
+  Rs.clear();
+  aggs.clear();
+  while (As.back().n > max_coarse && (int)As.size() < max_levels) {
+    const HostCsr &Al = As.back();
+    const std::vector<double> d = diagonal(Al);
+    for (double di : d)
+      if (!(di > 0.0)) {
+        err = "a diagonal entry is not positive";
+        return false;
+      }
+    std::vector<int64_t> agg;
+    const int64_t nc = aggregate(Al, d, std::ldexp(theta, -(int)(As.size() - 1)), agg);
+    if (nc == 0 || (double)nc >= 0.9 * (double)Al.n) break;
+    HostCsr P = prolongator(Al, d, agg, nc);
+    HostCsr R = transpose(P);
+    HostCsr Ac = multiply(R, multiply(Al, P));
+    Ps.push_back(std::move(P));
+    Rs.push_back(std::move(R));
+    aggs.push_back(std::move(agg));
+    As.push_back(std::move(Ac));
+  }
+  return true;
+}
+
 }  // namespace
 
 // ---- the device hierarchy -------------------------------------------------
@@ -488,29 +520,14 @@ int ssp_set_amg(ssp_handle *h, ssp_matrix *A, const ssp_amg_opts *opts) {
     HIPCHK(h, hipMemcpy(F.v.data(), A->csr.val, sizeof(double) * nnz, hipMemcpyDeviceToHost));
   }
   amg_free(A);
+  std::vector<HostCsr> As, Ps, Rs;
+  std::vector<std::vector<int64_t>> aggs;
+  std::string why;
+  if (!build_levels(F, theta, max_coarse, max_levels, As, Ps, Rs, aggs, why))
+    return fail(h, SSP_EINVAL, "ssp_set_amg: " + why);
   AmgHier *H = new AmgHier;
   H->omega = omega;
   H->sweeps = sweeps;
-  std::vector<HostCsr> As{F};
-  std::vector<HostCsr> Ps, Rs;
-  while (As.back().n > max_coarse && (int)As.size() < max_levels) {
-    const HostCsr &Al = As.back();
-    const std::vector<double> d = diagonal(Al);
-    for (double di : d)
-      if (!(di > 0.0)) {
-        delete H;
-        return fail(h, SSP_EINVAL, "ssp_set_amg: a diagonal entry is not positive");
-      }
-    std::vector<int64_t> agg;
-    const int64_t nc = aggregate(Al, d, std::ldexp(theta, -(int)(As.size() - 1)), agg);
-    if (nc == 0 || (double)nc >= 0.9 * (double)Al.n) break;
-    HostCsr P = prolongator(Al, d, agg, nc);
-    HostCsr R = transpose(P);
-    HostCsr Ac = multiply(R, multiply(Al, P));
-    Ps.push_back(std::move(P));
-    Rs.push_back(std::move(R));
-    As.push_back(std::move(Ac));
-  }
   if (As.back().n > SSP_AMG_DENSE_MAX) {
     delete H;
     return fail(h, SSP_EUNSUPPORTED, "ssp_set_amg: the coarsest level has " +
