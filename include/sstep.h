@@ -403,6 +403,19 @@ int ssp_net_params(ssp_net *net, float **params, float **grads, int64_t *count);
  * ssp_net_backward. */
 int ssp_net_forward(ssp_net *net, const float *in, int batch, float *out);
 
+/* Inference for one problem, every step on the device: the input channels
+ * log k and f / rms(f), with rms(f) = sqrt(sum f^2 / n) in FP64 (1 when f is
+ * zero), the forward pass (the decoder reads its upsampled and concatenated
+ * inputs straight from the two levels instead of building them), and the
+ * FP64 output x0 = y rms(f) out_scale.  logk, f: DEVICE FP64 [D][H][W];
+ * x0: DEVICE FP64 [D][H][W], not aliasing them.  The result equals
+ * ssp_net_forward on the FP32 pair (log k, f / rms(f)) followed by that
+ * scaling.  Asynchronous on the handle's stream; SSP_EINVAL for a null
+ * pointer or a non-finite out_scale.  The activations it leaves are not a
+ * training forward's: ssp_net_backward afterwards returns SSP_EINVAL. */
+int ssp_net_predict(ssp_net *net, const double *logk, const double *f, double out_scale,
+                    double *x0);
+
 /* Squared-error loss of the last forward's output y against target (DEVICE
  * FP32, batch*D*H*W): writes dy = 2 (y - t) / N (DEVICE) and, if loss is a
  * HOST pointer, the mean squared error (synchronises). */

@@ -180,12 +180,23 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const bf16 *__restrict__ in, 
 // identical.  MODE 1 reads the taps mirrored (q = p - o).  Dynamic LDS:
 // (CTZ+2)(CTY+2)(CTX+2) * cin BF16 values.
 constexpr int CTX = 16, CTY = 4, CTZ = 2;
+constexpr int kTiledMaxCin = 64;   // widest input the staged form takes
+// A convolution input formed on the fly as the concatenation of a coarser
+// tensor upsampled by kUp (nearest neighbour: channels 0 .. cu-1) and the
+// tensor `in` (channels cu .. cin-1), the buffer that k_up_concat writes,
+// read in the staging loop instead; up == nullptr: `in` holds all cin.
+struct UpSrc {
+  const bf16 *up;
+  Grid3 gu;
+  int cu;
+};
+
 template <int MODE, int NS>
 __global__ __launch_bounds__(256) void k_conv_tiled(const bf16 *__restrict__ in, int cin, Grid3 g,
                                                     const bf16 *__restrict__ wt, int kp,
                                                     const float *__restrict__ bias, int relu,
                                                     float *__restrict__ out_f,
-                                                    bf16 *__restrict__ out_b) {
+                                                    bf16 *__restrict__ out_b, UpSrc us) {
   constexpr int HX = CTX + 2, HY = CTY + 2, HZ = CTZ + 2;
   extern __shared__ __align__(16) bf16 s_in[];
   // per 8-wide k group: the LDS offset of its tap and channel relative to a
@@ -220,14 +231,41 @@ __global__ __launch_bounds__(256) void k_conv_tiled(const bf16 *__restrict__ in,
   const int x0 = tx * CTX, y0 = ty * CTY, z0 = tz * CTZ;
   const int ng = cin / 8;
   const bf16x8 zero8 = {};
-  for (int e = threadIdx.x; e < HZ * HY * HX * ng; e += 256) {
-    const int pi = e / ng, cg = e - pi * ng;
-    const int hx = pi % HX, hy = (pi / HX) % HY, hz = pi / (HX * HY);
-    const int qx = x0 + hx - 1, qy = y0 + hy - 1, qz = z0 + hz - 1;
-    bf16x8 v = zero8;
-    if (qx >= 0 && qx < g.W && qy >= 0 && qy < g.H && qz >= 0 && qz < g.D)
-      v = *(const bf16x8 *)(in + encode(b, qz, qy, qx, g) * cin + cg * 8);
-    *(bf16x8 *)(s_in + (int64_t)pi * cin + cg * 8) = v;
+  // loads are issued in batches of kStageBatch per thread before their LDS
+  // stores, so a 48-channel tile costs three round trips to memory instead
+  // of ten (a larger batch costs registers and occupancy; measured)
+  constexpr int kStageBatch = 4;
+  const int total = HZ * HY * HX * ng;
+  for (int e0 = threadIdx.x; e0 < total; e0 += 256 * kStageBatch) {
+    bf16x8 sv[kStageBatch];
+#pragma unroll
+    for (int i = 0; i < kStageBatch; ++i) {
+      const int e = e0 + 256 * i;
+      sv[i] = zero8;
+      if (e < total) {
+        const int pi = e / ng, cg = e - pi * ng;
+        const int hx = pi % HX, hy = (pi / HX) % HY, hz = pi / (HX * HY);
+        const int qx = x0 + hx - 1, qy = y0 + hy - 1, qz = z0 + hz - 1;
+        if (qx >= 0 && qx < g.W && qy >= 0 && qy < g.H && qz >= 0 && qz < g.D) {
+          const bf16 *src;
+          if (!us.up)
+            src = in + encode(b, qz, qy, qx, g) * cin + cg * 8;
+          else if (cg * 8 < us.cu)
+            src = us.up + encode(b, qz / kUp, qy / kUp, qx / kUp, us.gu) * us.cu + cg * 8;
+          else
+            src = in + encode(b, qz, qy, qx, g) * (cin - us.cu) + (cg * 8 - us.cu);
+          sv[i] = *(const bf16x8 *)src;
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kStageBatch; ++i) {
+      const int e = e0 + 256 * i;
+      if (e < total) {
+        const int pi = e / ng, cg = e - pi * ng;
+        *(bf16x8 *)(s_in + (int64_t)pi * cin + cg * 8) = sv[i];
+      }
+    }
   }
   __syncthreads();
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
@@ -245,24 +283,28 @@ __global__ __launch_bounds__(256) void k_conv_tiled(const bf16 *__restrict__ in,
   for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
     for (int n = 0; n < NS; ++n) acc[mt][n] = f32x4{0.f, 0.f, 0.f, 0.f};
-  // KU k chunks of 32 per step: every offset, weight and operand load of the
-  // step is issued before its products, so one round trip serves 2 KU NS
-  // matrix-core operations (chunks past kp re-read the last one and are
-  // skipped, a uniform test); fewer chunks for wide outputs (registers)
+  // K k chunks of 32 per step: every offset, weight and operand load of the
+  // step is issued before its products, so one round trip serves 2 K NS
+  // matrix-core operations.  Whole steps of KU chunks first, then one step
+  // of the remaining chunks: no branch inside a step, so the accumulators
+  // stay in the matrix-core registers.  The chunk order is
+  // the same as a plain loop's.  Fewer chunks per step for wide outputs
+  // (registers).
   constexpr int KU = NS >= 3 ? 2 : 4;
   const bf16 *wl = wt + (int64_t)m * kp + gq * 8;   // this lane's weight row, n = 0
-  for (int kc = 0; kc < kp; kc += 32 * KU) {
-    int off[KU];
-    bf16x8 w[KU][NS], a[KU][2];
+  auto step = [&](int kc, auto kcount) {
+    constexpr int K = decltype(kcount)::value;
+    int off[K];
+    bf16x8 w[K][NS], a[K][2];
 #pragma unroll
-    for (int u = 0; u < KU; ++u) {
-      const int k = kc + 32 * u < kp ? kc + 32 * u : kp - 32;
+    for (int u = 0; u < K; ++u) {
+      const int k = kc + 32 * u;
       off[u] = s_off[(k >> 3) + gq];
 #pragma unroll
       for (int n = 0; n < NS; ++n) w[u][n] = *(const bf16x8 *)(wl + (int64_t)n * 16 * kp + k);
     }
 #pragma unroll
-    for (int u = 0; u < KU; ++u)
+    for (int u = 0; u < K; ++u)
 #pragma unroll
       for (int mt = 0; mt < 2; ++mt) {
         // padding groups read the lane's own point (always staged) and use zero
@@ -271,15 +313,21 @@ __global__ __launch_bounds__(256) void k_conv_tiled(const bf16 *__restrict__ in,
         a[u][mt] = pad ? zero8 : v;
       }
 #pragma unroll
-    for (int u = 0; u < KU; ++u) {
-      if (kc + 32 * u < kp) {
+    for (int u = 0; u < K; ++u)
 #pragma unroll
-        for (int n = 0; n < NS; ++n)
+      for (int n = 0; n < NS; ++n)
 #pragma unroll
-          for (int mt = 0; mt < 2; ++mt)
-            acc[mt][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u][mt], w[u][n], acc[mt][n], 0, 0, 0);
-      }
-    }
+        for (int mt = 0; mt < 2; ++mt)
+          acc[mt][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u][mt], w[u][n], acc[mt][n], 0, 0, 0);
+  };
+  const int kfull = kp - kp % (32 * KU);
+  for (int kc = 0; kc < kfull; kc += 32 * KU) step(kc, std::integral_constant<int, KU>{});
+  // the remaining chunks (fewer than KU) as one step
+  switch ((kp - kfull) / 32) {
+    case 1: step(kfull, std::integral_constant<int, 1>{}); break;
+    case 2: if constexpr (KU > 2) step(kfull, std::integral_constant<int, 2>{}); break;
+    case 3: if constexpr (KU > 3) step(kfull, std::integral_constant<int, 3>{}); break;
+    default: break;
   }
   const int cout = NS * 16;
 #pragma unroll
@@ -544,15 +592,88 @@ __global__ __launch_bounds__(256) void k_slice(const float *__restrict__ src, in
   dst[i] = src[p * ct + off + (i - p * c_n)];
 }
 
+// 1x1 head of point p: sum over the 16 channels in order, then the bias.
+__device__ __forceinline__ float head_out(const bf16 *__restrict__ a, int64_t p,
+                                          const float *__restrict__ w, const float *__restrict__ b) {
+  float s = 0.0f;
+  for (int c = 0; c < kHeadC; ++c) s += (float)a[p * kHeadC + c] * w[c];
+  return s + b[0];
+}
+
 // 1x1 head: y[p] = sum_c a[p, c] w[c] + b.
 __global__ __launch_bounds__(256) void k_head(const bf16 *__restrict__ a, int64_t P,
                                               const float *__restrict__ w, const float *__restrict__ b,
                                               float *__restrict__ y) {
   const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (p >= P) return;
-  float s = 0.0f;
-  for (int c = 0; c < kHeadC; ++c) s += (float)a[p * kHeadC + c] * w[c];
-  y[p] = s + b[0];
+  y[p] = head_out(a, p, w, b);
+}
+
+// Inference input and output for one problem (batch 1), in the form the
+// training data take: input channels log k and f / rms(f) (the rest zero),
+// output x0 = y rms(f) out_scale in FP64.  rms(f) = sqrt(sum f^2 / P) in
+// FP64 from per-block partial sums added in block order (1 if it is 0).
+__global__ __launch_bounds__(256) void k_sumsq(const double *__restrict__ f, int64_t P,
+                                               double *__restrict__ part) {
+  __shared__ double red[256];
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const double v = p < P ? f[p] : 0.0;
+  red[threadIdx.x] = v * v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_rms(const double *__restrict__ part, int nblk, int64_t P,
+                                             double *__restrict__ rms) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += 256) s += part[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double r = sqrt(red[0] / (double)P);
+    rms[0] = r > 0.0 ? r : 1.0;
+  }
+}
+
+// double -> FP32 -> BF16 with both roundings, as the FP32 input pair of
+// the training path gets them (left alone, the compiler turns the pair into
+// one rounding of the double, which differs where the FP32 value sits on a
+// BF16 tie); the empty asm keeps the FP32 value opaque
+__device__ __forceinline__ bf16 bf16_via_f32(double d) {
+  float t = (float)d;
+  asm volatile("" : "+v"(t));
+  return (bf16)t;
+}
+
+__global__ __launch_bounds__(256) void k_input_fields(const double *__restrict__ logk,
+                                                      const double *__restrict__ f, int64_t P,
+                                                      const double *__restrict__ rms,
+                                                      bf16 *__restrict__ x0) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= P) return;
+  bf16x8 v = {};
+  v[0] = bf16_via_f32(logk[p]);
+  v[1] = bf16_via_f32(f[p] / rms[0]);
+  *(bf16x8 *)(x0 + p * 8) = v;
+}
+
+__global__ __launch_bounds__(256) void k_head_scaled(const bf16 *__restrict__ a, int64_t P,
+                                                     const float *__restrict__ w,
+                                                     const float *__restrict__ b,
+                                                     const double *__restrict__ rms,
+                                                     double out_scale, double *__restrict__ x) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= P) return;
+  x[p] = (double)head_out(a, p, w, b) * (rms[0] * out_scale);
 }
 
 // Head backward: g_a[p, c] = dy[p] w[c]; per-block partial sums of the head
@@ -688,6 +809,7 @@ struct ssp_net {
   float *wpart = nullptr, *bpart = nullptr;
   int64_t wpart_len = 0;
   double *loss_part = nullptr;
+  double *fstat = nullptr;   // inference: per-block sums of f^2, then rms(f)
   float *head_part = nullptr;
   int batch = 0;  // batch of the last forward
   std::vector<void *> allocs;
@@ -717,17 +839,20 @@ Grid3 grid_level(const ssp_net *n, int level, int batch) {
 template <int MODE>
 int launch_conv(ssp_handle *h, const bf16 *in, int cin, Grid3 gi, Grid3 go, int stride,
                 const bf16 *wt, int kp, const float *bias, int relu, float *out_f, bf16 *out_b,
-                int cout) {
-  if (stride == 1 && cin <= 64) {
+                int cout, UpSrc us = UpSrc{nullptr, Grid3{}, 0}) {
+  const bool tiled = stride == 1 && cin <= kTiledMaxCin && cin % 8 == 0;
+  if (us.up && (!tiled || us.cu <= 0 || us.cu >= cin || us.cu % 8 != 0))
+    return fail(h, SSP_EINVAL, "conv: the fused upsampled input needs the staged form");
+  if (tiled) {
     // LDS-staged input tile (same results, far fewer cache gathers)
     const unsigned tiles = (unsigned)(((gi.W + CTX - 1) / CTX) * ((gi.H + CTY - 1) / CTY) *
                                       ((gi.D + CTZ - 1) / CTZ) * gi.B);
     const size_t lds = sizeof(bf16) * (CTZ + 2) * (CTY + 2) * (CTX + 2) * cin;
     switch (cout / 16) {
-      case 1: k_conv_tiled<MODE, 1><<<tiles, 256, lds, h->stream>>>(in, cin, gi, wt, kp, bias, relu, out_f, out_b); break;
-      case 2: k_conv_tiled<MODE, 2><<<tiles, 256, lds, h->stream>>>(in, cin, gi, wt, kp, bias, relu, out_f, out_b); break;
-      case 3: k_conv_tiled<MODE, 3><<<tiles, 256, lds, h->stream>>>(in, cin, gi, wt, kp, bias, relu, out_f, out_b); break;
-      case 4: k_conv_tiled<MODE, 4><<<tiles, 256, lds, h->stream>>>(in, cin, gi, wt, kp, bias, relu, out_f, out_b); break;
+      case 1: k_conv_tiled<MODE, 1><<<tiles, 256, lds, h->stream>>>(in, cin, gi, wt, kp, bias, relu, out_f, out_b, us); break;
+      case 2: k_conv_tiled<MODE, 2><<<tiles, 256, lds, h->stream>>>(in, cin, gi, wt, kp, bias, relu, out_f, out_b, us); break;
+      case 3: k_conv_tiled<MODE, 3><<<tiles, 256, lds, h->stream>>>(in, cin, gi, wt, kp, bias, relu, out_f, out_b, us); break;
+      case 4: k_conv_tiled<MODE, 4><<<tiles, 256, lds, h->stream>>>(in, cin, gi, wt, kp, bias, relu, out_f, out_b, us); break;
       default: return fail(h, SSP_EINVAL, "conv: unsupported channel count");
     }
     LAUNCHCHK(h);
@@ -764,10 +889,11 @@ int launch_wgrad(ssp_handle *h, const bf16 *x, int ci, Grid3 gi, Grid3 go, int s
 }
 
 // Forward of conv layer L: out = relu(conv(in) + b) in BF16.
-int layer_forward(ssp_net *n, int L, const bf16 *in, Grid3 gi, Grid3 go, bf16 *out) {
+int layer_forward(ssp_net *n, int L, const bf16 *in, Grid3 gi, Grid3 go, bf16 *out,
+                  UpSrc us = UpSrc{nullptr, Grid3{}, 0}) {
   const LayerDef &d = kDef[L];
   return launch_conv<0>(n->h, in, d.ci, gi, go, d.stride, n->wf[L], n->kpf[L],
-                        n->params + n->b_off[L], 1, nullptr, out, d.co);
+                        n->params + n->b_off[L], 1, nullptr, out, d.co, us);
 }
 
 // Backward of conv layer L given dz (BF16, after the ReLU mask): weight and
@@ -793,6 +919,46 @@ int layer_backward(ssp_net *n, int L, const bf16 *in, Grid3 gi, Grid3 go, const 
     if (rc) return rc;
   }
   return SSP_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// BF16 GEMM operands from the FP32 master weights, all layers in one launch.
+int pack_weights(ssp_net *n) {
+  ssp_handle *h = n->h;
+  static_assert(kLayers == kPackLayers, "one packing table entry per layer");
+  PackTable t;
+  t.start[0] = 0;
+  for (int L = 0; L < kLayers; ++L) {
+    const int64_t nf = (int64_t)kDef[L].co * n->kpf[L], nb = (int64_t)kDef[L].ci * n->kpb[L];
+    t.w[L] = n->params + n->w_off[L];
+    t.wf[L] = n->wf[L];
+    t.wb[L] = n->wb[L];
+    t.ci[L] = kDef[L].ci;
+    t.co[L] = kDef[L].co;
+    t.kpf[L] = n->kpf[L];
+    t.kpb[L] = n->kpb[L];
+    t.start[L + 1] = t.start[L] + std::max(nf, nb);
+  }
+  k_pack_all<<<nblocks(t.start[kLayers]), 256, 0, h->stream>>>(t);
+  LAUNCHCHK(h);
+  return SSP_OK;
+}
+
+// Encoder (x0 -> e1b, the 32-channel level and the bottleneck) of the
+// network on the grids g.
+int encoder_forward(ssp_net *n, const Grid3 *g) {
+  int rc;
+  if ((rc = layer_forward(n, L_E1A, n->x0, g[0], g[0], n->a1))) return rc;
+  if ((rc = layer_forward(n, L_E1B, n->a1, g[0], g[0], n->a2))) return rc;
+  if ((rc = layer_forward(n, L_D1A, n->a2, g[0], g[1], n->h1))) return rc;
+  if ((rc = layer_forward(n, L_D1B, n->h1, g[1], g[2], n->d1))) return rc;
+  if ((rc = layer_forward(n, L_E2, n->d1, g[2], g[2], n->a3))) return rc;
+  if ((rc = layer_forward(n, L_D2A, n->a3, g[2], g[3], n->h2))) return rc;
+  if ((rc = layer_forward(n, L_D2B, n->h2, g[3], g[4], n->d2))) return rc;
+  return layer_forward(n, L_BOTT, n->d2, g[4], g[4], n->a4);
 }
 
 }  // namespace
@@ -866,6 +1032,7 @@ int ssp_net_create(ssp_handle *h, int D, int H, int W, int max_batch, uint64_t s
   A((void **)&n->wpart, sizeof(float) * n->wpart_len);
   A((void **)&n->bpart, sizeof(float) * 64 * 48);
   A((void **)&n->loss_part, sizeof(double) * nblocks(P[0]));
+  A((void **)&n->fstat, sizeof(double) * (nblocks((int64_t)D * H * W) + 1));
   A((void **)&n->head_part, sizeof(float) * nblocks(P[0]) * (kHeadC + 1));
   if (rc) {
     ssp_net_destroy(n);
@@ -909,38 +1076,13 @@ int ssp_net_forward(ssp_net *n, const float *in, int batch, float *out) {
   if (!n || !in || !out || batch < 1 || batch > n->max_batch) return SSP_EINVAL;
   ssp_handle *h = n->h;
   HIPCHK(h, hipSetDevice(h->device));
-  // BF16 GEMM operands from the FP32 master weights, all layers in one launch
-  {
-    static_assert(kLayers == kPackLayers, "one packing table entry per layer");
-    PackTable t;
-    t.start[0] = 0;
-    for (int L = 0; L < kLayers; ++L) {
-      const int64_t nf = (int64_t)kDef[L].co * n->kpf[L], nb = (int64_t)kDef[L].ci * n->kpb[L];
-      t.w[L] = n->params + n->w_off[L];
-      t.wf[L] = n->wf[L];
-      t.wb[L] = n->wb[L];
-      t.ci[L] = kDef[L].ci;
-      t.co[L] = kDef[L].co;
-      t.kpf[L] = n->kpf[L];
-      t.kpb[L] = n->kpb[L];
-      t.start[L + 1] = t.start[L] + std::max(nf, nb);
-    }
-    k_pack_all<<<nblocks(t.start[kLayers]), 256, 0, h->stream>>>(t);
-    LAUNCHCHK(h);
-  }
+  int rc = pack_weights(n);
+  if (rc) return rc;
   Grid3 g[5];
   for (int l = 0; l < 5; ++l) g[l] = grid_level(n, l, batch);
   k_input<<<nblocks(g[0].points()), 256, 0, h->stream>>>(in, g[0].points(), n->x0);
   LAUNCHCHK(h);
-  int rc;
-  if ((rc = layer_forward(n, L_E1A, n->x0, g[0], g[0], n->a1))) return rc;
-  if ((rc = layer_forward(n, L_E1B, n->a1, g[0], g[0], n->a2))) return rc;
-  if ((rc = layer_forward(n, L_D1A, n->a2, g[0], g[1], n->h1))) return rc;
-  if ((rc = layer_forward(n, L_D1B, n->h1, g[1], g[2], n->d1))) return rc;
-  if ((rc = layer_forward(n, L_E2, n->d1, g[2], g[2], n->a3))) return rc;
-  if ((rc = layer_forward(n, L_D2A, n->a3, g[2], g[3], n->h2))) return rc;
-  if ((rc = layer_forward(n, L_D2B, n->h2, g[3], g[4], n->d2))) return rc;
-  if ((rc = layer_forward(n, L_BOTT, n->d2, g[4], g[4], n->a4))) return rc;
+  if ((rc = encoder_forward(n, g))) return rc;
   k_up_concat<<<nblocks(g[2].points() * 8), 256, 0, h->stream>>>(n->a4, g[4], 32, n->a3, 32, g[2],
                                                                  kUp, n->c2);
   LAUNCHCHK(h);
@@ -953,6 +1095,34 @@ int ssp_net_forward(ssp_net *n, const float *in, int batch, float *out) {
                                                         n->params + n->head_b_off, out);
   LAUNCHCHK(h);
   n->batch = batch;
+  return SSP_OK;
+}
+
+int ssp_net_predict(ssp_net *n, const double *logk, const double *f, double out_scale,
+                    double *x0) {
+  if (!n || !logk || !f || !x0 || !std::isfinite(out_scale)) return SSP_EINVAL;
+  ssp_handle *h = n->h;
+  HIPCHK(h, hipSetDevice(h->device));
+  int rc = pack_weights(n);
+  if (rc) return rc;
+  Grid3 g[5];
+  for (int l = 0; l < 5; ++l) g[l] = grid_level(n, l, 1);
+  const int64_t P = g[0].points();
+  const unsigned nb = nblocks(P);
+  k_sumsq<<<nb, 256, 0, h->stream>>>(f, P, n->fstat + 1);
+  LAUNCHCHK(h);
+  k_rms<<<1, 256, 0, h->stream>>>(n->fstat + 1, (int)nb, P, n->fstat);
+  LAUNCHCHK(h);
+  k_input_fields<<<nb, 256, 0, h->stream>>>(logk, f, P, n->fstat, n->x0);
+  LAUNCHCHK(h);
+  if ((rc = encoder_forward(n, g))) return rc;
+  // the decoder reads its concatenated inputs straight from the two levels
+  if ((rc = layer_forward(n, L_U2, n->a3, g[2], g[2], n->a5, UpSrc{n->a4, g[4], 32}))) return rc;
+  if ((rc = layer_forward(n, L_U1, n->a2, g[0], g[0], n->a6, UpSrc{n->a5, g[2], 32}))) return rc;
+  k_head_scaled<<<nb, 256, 0, h->stream>>>(n->a6, P, n->params + n->head_w_off,
+                                          n->params + n->head_b_off, n->fstat, out_scale, x0);
+  LAUNCHCHK(h);
+  n->batch = 0;   // the activations are not a training forward's
   return SSP_OK;
 }
 

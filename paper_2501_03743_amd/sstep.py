@@ -39,7 +39,7 @@ EXPORTS = (
     "ssp_get_iterations", "ssp_get_residual_history", "ssp_get_true_residual",
     "ssp_get_profile", "ssp_status_string", "ssp_last_error", "ssp_solve_batch",
     "ssp_autotune_batch", "ssp_net_create", "ssp_net_destroy", "ssp_net_params",
-    "ssp_net_forward", "ssp_net_zero_grad", "ssp_net_backward", "ssp_net_loss",
+    "ssp_net_forward", "ssp_net_predict", "ssp_net_zero_grad", "ssp_net_backward", "ssp_net_loss",
     "ssp_net_adam_step", "ssp_net_get_state", "ssp_net_set_state", "ssp_conv3d",
     "ssp_conv3d_wgrad", "ssp_net_mfma_selftest", "ssp_get_warm_start", "ssp_get_restarts",
     "ssp_net_loss_h1", "ssp_matrix_csr_form", "ssp_mpk_noalloc", "ssp_cheb_basis",
@@ -133,6 +133,7 @@ def load():
         "ssp_net_destroy": (i32, [vp]),
         "ssp_net_params": (i32, [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(i64)]),
         "ssp_net_forward": (i32, [vp, vp, i32, vp]),
+        "ssp_net_predict": (i32, [vp, vp, vp, dbl, vp]),
         "ssp_net_zero_grad": (i32, [vp]),
         "ssp_net_backward": (i32, [vp, vp]),
         "ssp_net_loss": (i32, [vp, vp, vp, vp, C.POINTER(dbl)]),
@@ -651,6 +652,20 @@ class Net:
             out = torch.empty((B,) + self.shape, device=inp.device, dtype=torch.float32)
         _check_dev(out, torch.float32, inp.numel() // 2, "out")
         self._rc(load().ssp_net_forward(self._p, _ptr(inp), B, _ptr(out)), "ssp_net_forward")
+        return out
+
+    def predict(self, logk, f, out_scale, out=None):
+        """x0 = net(log k, f / rms(f)) rms(f) out_scale for one problem, all on
+        the device: logk, f float64 [D*H*W] -> float64 [D*H*W]."""
+        import torch
+        n = self.shape[0] * self.shape[1] * self.shape[2]
+        _check_dev(logk, torch.float64, n, "logk")
+        _check_dev(f, torch.float64, n, "f")
+        if out is None:
+            out = torch.empty(n, device=logk.device, dtype=torch.float64)
+        _check_dev(out, torch.float64, n, "out")
+        self._rc(load().ssp_net_predict(self._p, _ptr(logk), _ptr(f), float(out_scale), _ptr(out)),
+                 "ssp_net_predict")
         return out
 
     def loss(self, y, target, dy=None):

@@ -150,16 +150,10 @@ class WarmStart:
         return self.history
 
     def predict(self, logk, f, out=None):
-        """x0 (float64, n) for one problem."""
-        import torch
-        inp, fs = features(logk, f, self.shape)
-        y = self.net.forward(inp.unsqueeze(0).contiguous())
-        scale = fs * self.out_scale
-        x0 = y.reshape(-1).to(torch.float64) * scale
-        if out is not None:
-            out.copy_(x0)
-            return out
-        return x0
+        """x0 (float64, n) for one problem: features, network and output
+        scaling in one library call (the same values as `features`, a batch-1
+        forward and y * rms(f) * out_scale)."""
+        return self.net.predict(logk.reshape(-1), f.reshape(-1), self.out_scale, out=out)
 
     def close(self):
         self.net.close()

@@ -275,3 +275,49 @@ def test_net_rejects_bad_shapes(H):
     with pytest.raises(sstep.SspError):
         net.forward(torch.zeros((2, 8, 8, 8, 2), device="cuda"))
     net.close()
+
+
+def _fields(shape, seed):
+    """log k ~ N(0, 0.25) and a source f whose mean square is exactly 4
+    (values 0, +-2, +-4 in the proportions 3/8, 1/2, 1/8), so rms(f) = 2 and
+    f / rms(f) are exact in any summation order."""
+    g = np.random.default_rng(seed)
+    n = int(np.prod(shape))
+    assert n % 8 == 0
+    mag = np.concatenate([np.zeros(3 * n // 8), np.full(n // 2, 2.0), np.full(n // 8, 4.0)])
+    f = g.permutation(mag) * g.choice([-1.0, 1.0], n)
+    logk = 0.5 * g.standard_normal(n)
+    return logk, f
+
+
+@pytest.mark.parametrize("shape", [(40, 30, 26), (96, 96, 96)])
+def test_predict_matches_forward(H, shape):
+    """ssp_net_predict (features, forward with the decoder's concatenations
+    read in place, FP64 scaling) equals the composition of the FP32 input
+    pair, ssp_net_forward (which builds the concatenated buffers) and
+    y * rms(f) * out_scale, bit for bit."""
+    from paper_2501_03743_amd import sstep
+    P = U.init_params(3)
+    g = np.random.default_rng(8)
+    for k in P:
+        if k.endswith(".b"):
+            P[k] = 0.05 * g.standard_normal(P[k].shape)
+    net = H.net(shape, max_batch=1, seed=0)
+    net.set_state(flat_params(P).astype(np.float32))
+    out_scale = 0.37
+    for seed, zero_f in ((0, False), (1, True)):
+        logk, f = _fields(shape, seed)
+        if zero_f:
+            f[:] = 0.0
+        fs = float(np.sqrt(np.sum(f * f) / f.size)) or 1.0
+        inp = np.stack([logk, f / fs], axis=-1).astype(np.float32).reshape((1,) + shape + (2,))
+        y = net.forward(torch.from_numpy(inp).cuda())
+        ref = y.reshape(-1).double() * (fs * out_scale)
+        x = net.predict(torch.from_numpy(logk).cuda(), torch.from_numpy(f).cuda(), out_scale)
+        torch.cuda.synchronize()
+        assert torch.equal(x, ref), (seed, float((x - ref).abs().max()))
+        assert float(ref.abs().max()) > 0.0
+    # its activations are not a training forward's
+    with pytest.raises(sstep.SspError):
+        net.backward(torch.zeros(int(np.prod(shape)), device="cuda"))
+    net.close()
