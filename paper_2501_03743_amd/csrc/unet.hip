@@ -191,7 +191,7 @@ struct UpSrc {
   int cu;
 };
 
-template <int MODE, int NS>
+template <int MODE, int NS, int KU>
 __global__ __launch_bounds__(256) void k_conv_tiled(const bf16 *__restrict__ in, int cin, Grid3 g,
                                                     const bf16 *__restrict__ wt, int kp,
                                                     const float *__restrict__ bias, int relu,
@@ -287,10 +287,8 @@ __global__ __launch_bounds__(256) void k_conv_tiled(const bf16 *__restrict__ in,
   // step is issued before its products, so one round trip serves 2 K NS
   // matrix-core operations.  Whole steps of KU chunks first, then one step
   // of the remaining chunks: no branch inside a step, so the accumulators
-  // stay in the matrix-core registers.  The chunk order is
-  // the same as a plain loop's.  Fewer chunks per step for wide outputs
-  // (registers).
-  constexpr int KU = NS >= 3 ? 2 : 4;
+  // stay in the matrix-core registers.  The chunk order is the same as a
+  // plain loop's, whatever KU.
   const bf16 *wl = wt + (int64_t)m * kp + gq * 8;   // this lane's weight row, n = 0
   auto step = [&](int kc, auto kcount) {
     constexpr int K = decltype(kcount)::value;
@@ -848,11 +846,20 @@ int launch_conv(ssp_handle *h, const bf16 *in, int cin, Grid3 gi, Grid3 go, int 
     const unsigned tiles = (unsigned)(((gi.W + CTX - 1) / CTX) * ((gi.H + CTY - 1) / CTY) *
                                       ((gi.D + CTZ - 1) / CTZ) * gi.B);
     const size_t lds = sizeof(bf16) * (CTZ + 2) * (CTY + 2) * (CTX + 2) * cin;
+    // k chunks per step (KU): 2 for the wide outputs (registers) and for
+    // narrow inputs (fewer chunks; the occupancy that fewer registers allow
+    // hides more latency), 4 otherwise (measured)
+    const bool narrow = cin <= 16;
     switch (cout / 16) {
-      case 1: k_conv_tiled<MODE, 1><<<tiles, 256, lds, h->stream>>>(in, cin, gi, wt, kp, bias, relu, out_f, out_b, us); break;
-      case 2: k_conv_tiled<MODE, 2><<<tiles, 256, lds, h->stream>>>(in, cin, gi, wt, kp, bias, relu, out_f, out_b, us); break;
-      case 3: k_conv_tiled<MODE, 3><<<tiles, 256, lds, h->stream>>>(in, cin, gi, wt, kp, bias, relu, out_f, out_b, us); break;
-      case 4: k_conv_tiled<MODE, 4><<<tiles, 256, lds, h->stream>>>(in, cin, gi, wt, kp, bias, relu, out_f, out_b, us); break;
+      case 1:
+        if (narrow)
+          k_conv_tiled<MODE, 1, 2><<<tiles, 256, lds, h->stream>>>(in, cin, gi, wt, kp, bias, relu, out_f, out_b, us);
+        else
+          k_conv_tiled<MODE, 1, 4><<<tiles, 256, lds, h->stream>>>(in, cin, gi, wt, kp, bias, relu, out_f, out_b, us);
+        break;
+      case 2: k_conv_tiled<MODE, 2, 4><<<tiles, 256, lds, h->stream>>>(in, cin, gi, wt, kp, bias, relu, out_f, out_b, us); break;
+      case 3: k_conv_tiled<MODE, 3, 2><<<tiles, 256, lds, h->stream>>>(in, cin, gi, wt, kp, bias, relu, out_f, out_b, us); break;
+      case 4: k_conv_tiled<MODE, 4, 2><<<tiles, 256, lds, h->stream>>>(in, cin, gi, wt, kp, bias, relu, out_f, out_b, us); break;
       default: return fail(h, SSP_EINVAL, "conv: unsupported channel count");
     }
     LAUNCHCHK(h);
