@@ -358,17 +358,21 @@ __global__ __launch_bounds__(256) void k_conv_tiled(const bf16 *__restrict__ in,
 // (BF16), so a lane's operand (8 consecutive points of one channel) is one
 // 16-byte LDS read; the 16 x 16 output tiles are spread over the four waves
 // (TPW tiles per wave).  ci is padded to 16 with zero rows.  Tap-0 blocks
-// also sum dz per channel for the bias gradient (bpart[blk][co]).
-template <int TPW>
+// also sum dz per channel for the bias gradient (bpart[blk][co]).  KC
+// points per chunk, for at most CX input and CD output channels: the
+// narrow layers take longer chunks in the same LDS, and every load of a
+// chunk is issued before its LDS stores, so a round trip to memory moves
+// more points (the chunk loop waits for one round trip per chunk).  The
+// points are multiplied in the same order whatever KC, so the sums are too.
+template <int TPW, int KC, int CX, int CD>
 __global__ __launch_bounds__(256) void k_wgrad_mfma(const bf16 *__restrict__ xin, int ci_n,
                                                     Grid3 gi, Grid3 go, int stride,
                                                     const bf16 *__restrict__ dz, int co_n,
                                                     int64_t pts_per_blk, float *__restrict__ part,
                                                     float *__restrict__ bpart) {
-  constexpr int KC = 64;        // points per staged chunk (two k-steps)
   constexpr int LDP = KC + 8;   // padded LDS row, in BF16 elements
-  __shared__ __align__(16) bf16 sx[80][LDP];
-  __shared__ __align__(16) bf16 sd[48][LDP];
+  __shared__ __align__(16) bf16 sx[CX][LDP];
+  __shared__ __align__(16) bf16 sd[CD][LDP];
   const int t = blockIdx.y;
   const int dz_ = t / 9 - 1, dy_ = (t / 3) % 3 - 1, dx_ = t % 3 - 1;
   const int cim = (ci_n + 15) / 16 * 16;
@@ -386,27 +390,53 @@ __global__ __launch_bounds__(256) void k_wgrad_mfma(const bf16 *__restrict__ xin
     sx[ci_n + e / LDP][e % LDP] = (bf16)0.0f;
   const bf16x8 zero8 = {};
   const int ngx = ci_n / 8, ngd = co_n / 8;
+  constexpr int NX = (KC * (CX / 8) + 255) / 256;   // x loads per thread per chunk
+  constexpr int ND = (KC * (CD / 8) + 255) / 256;   // dz loads per thread per chunk
   for (int64_t pb = p0; pb < p1; pb += KC) {
-    for (int e = threadIdx.x; e < KC * ngx; e += 256) {
-      const int j = e / ngx, cg = e - j * ngx;
-      const int64_t p = pb + j;
-      bf16x8 v = zero8;
-      if (p < p1) {
-        int b, z, y, x;
-        decode(p, go, b, z, y, x);
-        const int qz = stride * z + dz_, qy = stride * y + dy_, qx = stride * x + dx_;
-        if (qz >= 0 && qz < gi.D && qy >= 0 && qy < gi.H && qx >= 0 && qx < gi.W)
-          v = *(const bf16x8 *)(xin + encode(b, qz, qy, qx, gi) * ci_n + cg * 8);
+    bf16x8 vx[NX], vd[ND];
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      vx[i] = zero8;
+      if (e < KC * ngx) {
+        const int j = e / ngx, cg = e - j * ngx;
+        const int64_t p = pb + j;
+        if (p < p1) {
+          int b, z, y, x;
+          decode(p, go, b, z, y, x);
+          const int qz = stride * z + dz_, qy = stride * y + dy_, qx = stride * x + dx_;
+          if (qz >= 0 && qz < gi.D && qy >= 0 && qy < gi.H && qx >= 0 && qx < gi.W)
+            vx[i] = *(const bf16x8 *)(xin + encode(b, qz, qy, qx, gi) * ci_n + cg * 8);
+        }
       }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) sx[cg * 8 + u][j] = v[u];
     }
-    for (int e = threadIdx.x; e < KC * ngd; e += 256) {
-      const int j = e / ngd, cg = e - j * ngd;
-      const int64_t p = pb + j;
-      const bf16x8 v = (p < p1) ? *(const bf16x8 *)(dz + p * co_n + cg * 8) : zero8;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) sd[cg * 8 + u][j] = v[u];
+    for (int i = 0; i < ND; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      vd[i] = zero8;
+      if (e < KC * ngd) {
+        const int j = e / ngd, cg = e - j * ngd;
+        const int64_t p = pb + j;
+        if (p < p1) vd[i] = *(const bf16x8 *)(dz + p * co_n + cg * 8);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      if (e < KC * ngx) {
+        const int j = e / ngx, cg = e - j * ngx;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) sx[cg * 8 + u][j] = vx[i][u];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < ND; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      if (e < KC * ngd) {
+        const int j = e / ngd, cg = e - j * ngd;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) sd[cg * 8 + u][j] = vd[i][u];
+      }
     }
     __syncthreads();
     if (t == 0 && threadIdx.x < co_n)
@@ -884,12 +914,19 @@ int launch_wgrad(ssp_handle *h, const bf16 *x, int ci, Grid3 gi, Grid3 go, int s
                  const bf16 *dz, int co, int nblk, int64_t per, float *part, float *bpart) {
   const int ntile = ((ci + 15) / 16) * (co / 16);
   const dim3 grid(nblk, 27);
-  switch ((ntile + 3) / 4) {
-    case 1: k_wgrad_mfma<1><<<grid, 256, 0, h->stream>>>(x, ci, gi, go, stride, dz, co, per, part, bpart); break;
-    case 2: k_wgrad_mfma<2><<<grid, 256, 0, h->stream>>>(x, ci, gi, go, stride, dz, co, per, part, bpart); break;
-    case 3: k_wgrad_mfma<3><<<grid, 256, 0, h->stream>>>(x, ci, gi, go, stride, dz, co, per, part, bpart); break;
-    case 4: k_wgrad_mfma<4><<<grid, 256, 0, h->stream>>>(x, ci, gi, go, stride, dz, co, per, part, bpart); break;
-    default: return fail(h, SSP_EINVAL, "weight gradient: unsupported channel counts");
+  // chunk length by channel counts (about 17 KB of LDS per workgroup each)
+  if (ci <= 16 && co <= 16) {
+    k_wgrad_mfma<1, 256, 16, 16><<<grid, 256, 0, h->stream>>>(x, ci, gi, go, stride, dz, co, per, part, bpart);
+  } else if (ci <= 48 && co <= 16) {
+    k_wgrad_mfma<1, 128, 48, 16><<<grid, 256, 0, h->stream>>>(x, ci, gi, go, stride, dz, co, per, part, bpart);
+  } else {
+    switch ((ntile + 3) / 4) {
+      case 1: k_wgrad_mfma<1, 64, 80, 48><<<grid, 256, 0, h->stream>>>(x, ci, gi, go, stride, dz, co, per, part, bpart); break;
+      case 2: k_wgrad_mfma<2, 64, 80, 48><<<grid, 256, 0, h->stream>>>(x, ci, gi, go, stride, dz, co, per, part, bpart); break;
+      case 3: k_wgrad_mfma<3, 64, 80, 48><<<grid, 256, 0, h->stream>>>(x, ci, gi, go, stride, dz, co, per, part, bpart); break;
+      case 4: k_wgrad_mfma<4, 64, 80, 48><<<grid, 256, 0, h->stream>>>(x, ci, gi, go, stride, dz, co, per, part, bpart); break;
+      default: return fail(h, SSP_EINVAL, "weight gradient: unsupported channel counts");
+    }
   }
   LAUNCHCHK(h);
   return SSP_OK;
