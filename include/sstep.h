@@ -454,7 +454,8 @@ int ssp_conv3d(ssp_handle *h, int mode, const float *in, int B, int D, int H, in
                const float *w, int co, int stride, float *out);
 
 /* Weight and bias gradients of that convolution for input x and output
- * gradient dz (DEVICE, FP32, rounded to BF16): dw [27][ci][co], db [co]. */
+ * gradient dz (DEVICE, FP32, rounded to BF16): dw [27][ci][co], db [co].
+ * Grids of 2^31 points or more (batch included) return SSP_EINVAL. */
 int ssp_conv3d_wgrad(ssp_handle *h, const float *x, int B, int D, int H, int W, int ci,
                      const float *dz, int co, int stride, float *dw, float *db);
 

@@ -58,6 +58,18 @@ __device__ __forceinline__ void decode(int64_t p, const Grid3 &g, int &b, int &z
   b = (int)(t / g.D);
 }
 
+// The same split for point indices below 2^31, in 32-bit arithmetic (the
+// 64-bit divisions cost several times more instructions).
+__device__ __forceinline__ void decode32(uint32_t p, const Grid3 &g, int &b, int &z, int &y,
+                                         int &x) {
+  const uint32_t W = (uint32_t)g.W, H = (uint32_t)g.H, D = (uint32_t)g.D;
+  const uint32_t t = p / W, t2 = t / H, bb = t2 / D;
+  x = (int)(p - t * W);
+  y = (int)(t - t2 * H);
+  z = (int)(t2 - bb * D);
+  b = (int)bb;
+}
+
 __device__ __forceinline__ int64_t encode(int b, int z, int y, int x, const Grid3 &g) {
   return (((int64_t)b * g.D + z) * g.H + y) * g.W + x;
 }
@@ -403,7 +415,7 @@ __global__ __launch_bounds__(256) void k_wgrad_mfma(const bf16 *__restrict__ xin
         const int64_t p = pb + j;
         if (p < p1) {
           int b, z, y, x;
-          decode(p, go, b, z, y, x);
+          decode32((uint32_t)p, go, b, z, y, x);   // P < 2^31 (host check)
           const int qz = stride * z + dz_, qy = stride * y + dy_, qx = stride * x + dx_;
           if (qz >= 0 && qz < gi.D && qy >= 0 && qy < gi.H && qx >= 0 && qx < gi.W)
             vx[i] = *(const bf16x8 *)(xin + encode(b, qz, qy, qx, gi) * ci_n + cg * 8);
@@ -913,6 +925,8 @@ int launch_conv(ssp_handle *h, const bf16 *in, int cin, Grid3 gi, Grid3 go, int 
 int launch_wgrad(ssp_handle *h, const bf16 *x, int ci, Grid3 gi, Grid3 go, int stride,
                  const bf16 *dz, int co, int nblk, int64_t per, float *part, float *bpart) {
   const int ntile = ((ci + 15) / 16) * (co / 16);
+  if (go.points() > INT32_MAX || gi.points() > INT32_MAX)
+    return fail(h, SSP_EINVAL, "weight gradient: grids of 2^31 points or more are not supported");
   const dim3 grid(nblk, 27);
   // chunk length by channel counts (about 17 KB of LDS per workgroup each)
   if (ci <= 16 && co <= 16) {
