@@ -819,10 +819,10 @@ def main():
 
     config4 = None
     if not args.skip_warmstart:
-        # bounded: 1000 training solutions, 24 epochs, 50 held-out seeds
-        config4 = bench_warmstart(H, n_train=1000, n_eval=50, epochs=24, n_loose=20, n_forms=20,
+        # bounded: 1500 training solutions, 24 epochs, 50 held-out seeds
+        config4 = bench_warmstart(H, n_train=1500, n_eval=50, epochs=24, n_loose=20, n_forms=20,
                                   log=lambda m: log("warmstart: " + m))
-        config4["budget"] = "bounded: 1000 training solutions, 24 epochs, 50 held-out seeds"
+        config4["budget"] = "bounded: 1500 training solutions, 24 epochs, 50 held-out seeds"
         log("warm start done")
 
     out = {
